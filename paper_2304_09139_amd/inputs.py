@@ -1,0 +1,58 @@
+"""Seeded synthetic inputs shared by the tests, the oracle checks and the benchmark.
+
+This module only draws random numbers and formats them; it contains none of the
+method's arithmetic.  The paper starts every quench from a Poisson point
+process, i.e. independent uniform positions in the periodic box ("Simulations"
+section).  Here each fractional coordinate is an exact 106-bit dyadic
+u = a 2^-53 + b 2^-106 with a, b the top 53 bits of two SplitMix64 outputs
+(Steele, Lea and Flood, OOPSLA 2014), stored as a normalised hi/lo pair:
+hi = u rounded to the nearest double and lo = u - hi exactly.
+
+Positions use the ``float64[2, d, N]`` layout (hi plane, lo plane) of the
+library's C interface.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, count: int, offset: int = 0) -> np.ndarray:
+    """Outputs offset .. offset+count-1 of the SplitMix64 stream started at ``seed``."""
+    with np.errstate(over="ignore"):
+        idx = np.arange(offset + 1, offset + count + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + idx * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def stream_seed(*keys: int) -> int:
+    """Fold a tuple of integers (config id, replica, ...) into one 64-bit seed."""
+    s = 0x243F6A8885A308D3
+    for k in keys:
+        s = int(splitmix64(s ^ (int(k) & 0xFFFFFFFFFFFFFFFF), 1)[0])
+    return s
+
+
+def uniform_positions(d: int, N: int, seed: int) -> np.ndarray:
+    """iid uniform fractional positions in [0, 1)^d as float64[2, d, N]."""
+    raw = splitmix64(seed, 2 * d * N).reshape(d, N, 2)
+    a = (raw[..., 0] >> np.uint64(11)).astype(np.float64)   # 53-bit integers, exact
+    b = (raw[..., 1] >> np.uint64(11)).astype(np.float64)
+    ta = a * 2.0 ** -53                                     # exact scalings
+    tb = b * 2.0 ** -106
+    hi = ta + tb                                            # one rounding: nearest double to u
+    lo = (ta - hi) + tb                                     # exact remainder u - hi
+    out = np.empty((2, d, N), dtype=np.float64)
+    out[0] = hi
+    out[1] = lo
+    return out
+
+
+def config_positions(cfg_id: int, d: int, N: int, replica: int = 0) -> np.ndarray:
+    """Positions for a named workload and replica (seed = stream_seed(cfg_id, replica))."""
+    return uniform_positions(d, N, stream_seed(cfg_id, replica))
