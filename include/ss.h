@@ -1,0 +1,183 @@
+/*
+ * ss.h -- C interface of libss, the MI355X (gfx950) double-double hot path of
+ * collective-coordinate optimisation for stealthy hyperuniform point patterns
+ * (Morse, Kim, Steinhardt, Torquato, arXiv:2304.09139).
+ *
+ * Problem (paper, "Definitions"): N points in a periodic hypercubic box of side
+ * L in R^d; wavevectors k = 2 pi n / L with integer n and 0 < |k| <= K;
+ * n~(k) = sum_j exp(-i k.r_j) (Eq. ntilde), S(k) = |n~(k)|^2 / N
+ * (Eq. structurefactor), S_max = max over the exclusion region (Eq. smax), and
+ * the energy of Eq. energy with its structure-independent term dropped, whose
+ * minimisation drives S(k) -> 0 inside the exclusion region.
+ *
+ * Conventions used by every entry point:
+ *  - Double-double (dd) arrays store a hi plane followed by a lo plane; the
+ *    value is hi + lo.
+ *  - Positions are FRACTIONAL coordinates u = r / L as double[2][d][N]
+ *    (pos[a*N + j] = hi of u_{j,a}, pos[(d + a)*N + j] = lo).  They need not
+ *    lie in [0, 1) (the energy is periodic) but must satisfy |u| < 2^20.
+ *  - The wavevector set is the half set H(R2) = { n in Z^d : 0 < |n|^2 <= R2,
+ *    first nonzero component > 0 }: by the inversion symmetry S(k) = S(-k)
+ *    only M of the 2M nonzero vectors in the ball are independent ("Definitions",
+ *    the paragraph defining chi).  Its canonical order is ascending |n|^2, ties by
+ *    ascending lexicographic order of (n_1, ..., n_d).
+ *  - Weights v_k are the dimensionless v~(k) / (eps0 L^d): v = 1 for the
+ *    Heaviside potential of the "Simulations" section.  With them
+ *        Phi = sum_{n in H} v_n |n~(k_n)|^2
+ *    which equals the paper's Phi / eps0 (the full +-k sum of Eq. energy folds
+ *    onto the half set).
+ *  - n~ outputs are double[4][M] = (C.hi, C.lo, S.hi, S.lo) in canonical
+ *    order, with C = sum_j cos(k.r_j), S = sum_j sin(k.r_j), n~ = C - i S.
+ *  - Device pointers are caller-owned (e.g. PyTorch tensors); the library
+ *    never frees them.  `stream` is a hipStream_t passed as void*; NULL means
+ *    the default stream.  Calls marked "async" only enqueue work on `stream`.
+ *  - Return codes: SS_OK (0), SS_PENDING (> 0, informative) or a negative
+ *    error.  Nothing aborts or throws across this interface.  HIP failures map
+ *    to SS_EHIP with detail in ss_last_error(); a fault inside an async launch
+ *    surfaces at the next synchronising call.
+ *  - Results are bitwise reproducible: every reduction has a fixed order and
+ *    launch shapes depend only on (d, N, M).
+ */
+#ifndef SS_H
+#define SS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SS_OK = 0,
+  SS_PENDING = 1,
+  SS_EINVAL = -1,    /* invalid argument (sizes, NULL pointers, workspace too small) */
+  SS_ENOMEM = -2,    /* device allocation failed                                       */
+  SS_EHIP = -3,      /* HIP runtime error                                              */
+  SS_ENOTFOUND = -4, /* unknown ticket                                                 */
+  SS_ESTATE = -5,    /* call not valid in the current state                            */
+  SS_ENUMERIC = -6   /* non-finite value met                                           */
+};
+
+typedef struct ss_ctx ss_ctx;
+
+/* A problem instance.  M must equal the size of H(R2) (ss_count).
+ * vkind: 0 -> v = 1 (v_dev ignored, may be NULL);
+ *        1 -> v = (1 - |k|/K)^2 with K^2 = (R2 + 1/2) (2 pi / L)^2, a weight
+ *             table that the caller fills with ss_weights;
+ *        2 -> an arbitrary positive caller table v_dev. */
+typedef struct {
+  int32_t d;     /* 1..4 */
+  int64_t N;     /* particles, >= 1 */
+  int64_t R2;    /* cutoff: |n|^2 <= R2, i.e. K = 2 pi sqrt(R2) / L */
+  int64_t M;     /* |H(R2)| */
+  double L;      /* box side, > 0 */
+  int32_t vkind; /* see above */
+} ss_problem;
+
+/* Create a context on HIP device `device` (the device is made current).  The
+ * context owns only its cached wavevector plans and a private stream for
+ * building them.  Returns SS_OK and *out, or SS_EINVAL / SS_EHIP. */
+int ss_create(int device, ss_ctx** out);
+
+/* Release the context and its plans.  NULL is accepted. */
+int ss_destroy(ss_ctx* ctx);
+
+/* Static description of a return code. */
+const char* ss_strerror(int code);
+
+/* Detail of the last error seen by this context ("" if none); the string lives
+ * until the next call on the context. */
+const char* ss_last_error(ss_ctx* ctx);
+
+/* Size of the half set H(R2): M.  Host only, pure.  SS_EINVAL for d outside
+ * 1..4 or R2 < 1. (The paper's count of M independent constraints,
+ * "Definitions", the paragraph defining chi.) */
+int ss_count(int d, int64_t R2, int64_t* M);
+
+/* Cutoff from the constraint fraction chi = M / (d (N - 1)) (same paragraph):
+ * the largest squared radius R2 that some lattice vector attains and whose
+ * count M(R2) does not exceed chi d (N - 1).  Host only, pure.  SS_EINVAL for
+ * d outside 1..4, N < 2, chi outside (0, 1/2) (the disordered regime the paper
+ * restricts to), or when no shell fits. */
+int ss_cutoff(int d, int64_t N, double chi, int64_t* R2, int64_t* M);
+
+/* Enumerate H(R2) in canonical order into n_dev (int32[M][d], device memory of
+ * `capacity` vectors) with integer GPU kernels; also caches the plan the
+ * energy kernels use for this (d, R2).  Pass n_dev = NULL for a size query.
+ * Synchronising.  *M receives |H(R2)|; SS_EINVAL if capacity < M. */
+int ss_wavevectors(ss_ctx* ctx, int d, int64_t R2, int32_t* n_dev, int64_t capacity, int64_t* M, void* stream);
+
+/* Fill v_dev (double[2][M], device) with the weights of prob->vkind (0 or 1)
+ * for the canonical list n_dev (from ss_wavevectors).  Async. */
+int ss_weights(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, double* v_dev, void* stream);
+
+/* Workspace bytes needed by ss_energy_grad (op = 0) or ss_minimize (op = 1)
+ * for this problem.  Builds the wavevector plan if needed (synchronising). */
+int ss_workspace_size(ss_ctx* ctx, const ss_problem* prob, int op, size_t* bytes);
+
+/* One evaluation of the energy and its gradient (the two O(MN) sums of the
+ * "Simulations" section):
+ *   phi_dev[2]   <- Phi = sum_{n in H} v_n (C_n^2 + S_n^2)          (Eq. energy)
+ *   smax_dev[2]  <- S_max = max_n (C_n^2 + S_n^2) / N (or NULL)      (Eq. smax)
+ *   grad_dev     <- dPhi/dr_{j,a} = (4 pi / L) sum_n v_n n_a (S_n c_jn - C_n s_jn)
+ *                   as double[2][d][N] (or NULL to skip the gradient pass);
+ *                   this is -F_j of Eq. force
+ *   nk_dev       <- n~ as double[4][M] in canonical order (or NULL)
+ * where c_jn, s_jn = cos, sin of k_n.r_j.  n_dev is the canonical list from
+ * ss_wavevectors for (d, R2); v_dev is double[2][M] (see vkind).  ws is device
+ * scratch of at least ss_workspace_size(op = 0) bytes.  Async; SS_EINVAL on
+ * bad sizes, NULL required pointers or a short workspace. */
+int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
+                   const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Options of the L-BFGS quench (ss_minimize).  The paper quenches with FIRE
+ * until Phi is as small as the precision allows ("Simulations" section); this
+ * library uses limited-memory BFGS with these rules:
+ *  - converged when S_max <= s_floor;
+ *  - direction -H g by the two-loop recursion over the last `history` pairs
+ *    (1..16), H0 = (s.y / y.y) I of the newest pair; with no pairs, or when
+ *    that is not a descent direction, the history is cleared and the step is
+ *    -g * step_cap * N^(-1/d) / max|g| (at most step_cap of the mean spacing);
+ *  - Armijo backtracking from alpha = 1 by halving: accept when
+ *    Phi(x + alpha p) <= Phi(x) + c1 alpha g.p; after max_halvings halvings a
+ *    failure is recorded, the history cleared and x kept;
+ *  - a pair (s, y) = (x_new - x, g_new - g) is kept only when s.y > 0;
+ *  - stalled when min Phi over the last stall_window iterations exceeds
+ *    stall_ratio * min Phi over the stall_window before, or after max_ls_fail
+ *    consecutive failures; stops after max_iter iterations. */
+typedef struct {
+  int32_t history;      /* 1..16 (8 is typical)   */
+  int64_t max_iter;     /* >= 0                   */
+  double s_floor;       /* stated S(k) floor      */
+  int32_t stall_window; /* >= 1, e.g. 50           */
+  double stall_ratio;   /* e.g. 0.99              */
+  double c1;            /* Armijo constant (0, 1) */
+  double step_cap;      /* > 0, e.g. 1e-2         */
+  int32_t max_halvings; /* >= 0                   */
+  int32_t max_ls_fail;  /* >= 1                   */
+} ss_min_opts;
+
+/* status: 0 converged (S_max <= s_floor), 1 stalled, 2 iteration cap,
+ * 3 non-finite energy */
+typedef struct {
+  int32_t status;
+  int64_t iters, evals, grad_evals;
+  double phi[2], smax[2];
+  double seconds;
+} ss_min_result;
+
+/* Quench pos_dev (double[2][d][N] fractional coordinates, updated in place and
+ * not wrapped into the unit cell) with the rules of ss_min_opts, every vector
+ * kept in device memory.  ws must hold ss_workspace_size(op = 1) bytes.
+ * Synchronising: returns when the run ends, with *out filled.  Returns SS_OK,
+ * SS_ENUMERIC if the energy is not finite (status 3), or an error. */
+int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev, double* pos_dev,
+                const ss_min_opts* opts, ss_min_result* out, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SS_H */

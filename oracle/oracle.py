@@ -259,8 +259,8 @@ def energy_grad(n, v, pos, L: float = 1.0, want_grad: bool = True):
 
 # --- minimiser ----------------------------------------------------------------
 
-DEFAULT_OPTS = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=30,
-                    stall_ratio=0.5, c1=1e-4, step_cap=1e-2, max_halvings=40, max_ls_fail=3)
+DEFAULT_OPTS = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=50,
+                    stall_ratio=0.99, c1=1e-4, step_cap=1e-2, max_halvings=40, max_ls_fail=3)
 
 STATUS = {0: "converged", 1: "stalled", 2: "max_iter"}
 

@@ -607,14 +607,17 @@ static int lbfgs_run(objective* o, int64_t nv, dd* x, const or_lbfgs_opts* op,
     dd* xt = (dd*)calloc((size_t)nv, sizeof(dd));
     dd* gt = (dd*)calloc((size_t)nv, sizeof(dd));
     dd* q = (dd*)calloc((size_t)nv, sizeof(dd));
-    dd* S = (dd*)calloc((size_t)nv * (size_t)m, sizeof(dd));
-    dd* Y = (dd*)calloc((size_t)nv * (size_t)m, sizeof(dd));
-    dd* rho = (dd*)calloc((size_t)m, sizeof(dd));
-    dd* alpha = (dd*)calloc((size_t)m, sizeof(dd));
+    /* m ring slots plus one spare that receives each candidate pair, so a pair
+     * rejected by the s.y > 0 test never overwrites a kept one */
+    dd* S = (dd*)calloc((size_t)nv * (size_t)(m + 1), sizeof(dd));
+    dd* Y = (dd*)calloc((size_t)nv * (size_t)(m + 1), sizeof(dd));
+    dd* rho = (dd*)calloc((size_t)(m + 1), sizeof(dd));
+    dd* alpha = (dd*)calloc((size_t)(m + 1), sizeof(dd));
+    int* ring = (int*)calloc((size_t)(m + 1), sizeof(int)); /* ring[0..hn) = slots, oldest first */
     int64_t W = op->stall_window;
     dd* fhist = (dd*)calloc((size_t)(op->max_iter + 2), sizeof(dd));
-    if (!g || !p || !xt || !gt || !q || !S || !Y || !rho || !alpha || !fhist) return -1;
-    int hn = 0, hstart = 0; /* ring buffer of pairs: oldest at hstart */
+    if (!g || !p || !xt || !gt || !q || !S || !Y || !rho || !alpha || !fhist || !ring) return -1;
+    int hn = 0;
     int ls_fail = 0;
     double nmean = pow((double)o->N, -1.0 / (double)(o->d > 0 ? o->d : 1));
     if (o->kind == 1) nmean = 1.0;
@@ -640,17 +643,17 @@ static int lbfgs_run(objective* o, int64_t nv, dd* x, const or_lbfgs_opts* op,
         if (!use_sd) {
             for (int64_t i = 0; i < nv; i++) q[i] = g[i];
             for (int h = hn - 1; h >= 0; h--) {
-                int slot = (hstart + h) % m;
+                int slot = ring[h];
                 alpha[slot] = dd_mul(rho[slot], vdot(nv, S + (int64_t)slot * nv, q));
                 for (int64_t i = 0; i < nv; i++) q[i] = dd_sub(q[i], dd_mul(alpha[slot], Y[(int64_t)slot * nv + i]));
             }
-            int newest = (hstart + hn - 1) % m;
+            int newest = ring[hn - 1];
             dd sy = vdot(nv, S + (int64_t)newest * nv, Y + (int64_t)newest * nv);
             dd yy = vdot(nv, Y + (int64_t)newest * nv, Y + (int64_t)newest * nv);
             dd gamma = dd_div(sy, yy);
             for (int64_t i = 0; i < nv; i++) q[i] = dd_mul(gamma, q[i]);
             for (int h = 0; h < hn; h++) {
-                int slot = (hstart + h) % m;
+                int slot = ring[h];
                 dd beta = dd_mul(rho[slot], vdot(nv, Y + (int64_t)slot * nv, q));
                 dd coef = dd_sub(alpha[slot], beta);
                 for (int64_t i = 0; i < nv; i++) q[i] = dd_add(q[i], dd_mul(coef, S[(int64_t)slot * nv + i]));
@@ -660,7 +663,7 @@ static int lbfgs_run(objective* o, int64_t nv, dd* x, const or_lbfgs_opts* op,
             if (!dd_lt(gp, dd_from(0.0))) use_sd = 1;
         }
         if (use_sd) {
-            hn = 0; hstart = 0;
+            hn = 0;
             dd gmax = dd_from(0.0); /* max_i |g_i|, compared in double-double */
             for (int64_t i = 0; i < nv; i++) {
                 dd ag = g[i].hi < 0.0 ? dd_neg(g[i]) : g[i];
@@ -685,22 +688,28 @@ static int lbfgs_run(objective* o, int64_t nv, dd* x, const or_lbfgs_opts* op,
         it++;
         if (!accepted) {
             ls_fail++;
-            hn = 0; hstart = 0;
+            hn = 0;
             if (ls_fail >= op->max_ls_fail) { fhist[it] = f; status = 1; break; }
             continue;
         }
         ls_fail = 0;
         obj_eval(o, nv, xt, &ft, &smt, gt);
         res->grad_evals++;
-        /* new pair s = x_new - x, y = g_new - g */
-        int slot = hn < m ? (hstart + hn) % m : hstart;
+        /* candidate pair s = x_new - x, y = g_new - g in a slot no kept pair uses */
+        int slot = 0;
+        for (;; slot++) {
+            int used = 0;
+            for (int h = 0; h < hn; h++) if (ring[h] == slot) used = 1;
+            if (!used) break;
+        }
         dd* s_new = S + (int64_t)slot * nv;
         dd* y_new = Y + (int64_t)slot * nv;
         for (int64_t i = 0; i < nv; i++) { s_new[i] = dd_sub(xt[i], x[i]); y_new[i] = dd_sub(gt[i], g[i]); }
         dd sy = vdot(nv, s_new, y_new);
-        if (dd_gt(sy, dd_from(0.0))) {
+        if (dd_gt(sy, dd_from(0.0))) {   /* keep it; drop the oldest beyond m */
             rho[slot] = dd_div(dd_from(1.0), sy);
-            if (hn < m) hn++; else hstart = (hstart + 1) % m;
+            if (hn == m) { for (int h = 1; h < m; h++) ring[h - 1] = ring[h]; hn--; }
+            ring[hn++] = slot;
         }
         for (int64_t i = 0; i < nv; i++) { x[i] = xt[i]; g[i] = gt[i]; }
         f = ft; smax = smt;
@@ -709,7 +718,7 @@ static int lbfgs_run(objective* o, int64_t nv, dd* x, const or_lbfgs_opts* op,
     res->iters = it;
     res->phi[0] = f.hi; res->phi[1] = f.lo;
     res->smax[0] = smax.hi; res->smax[1] = smax.lo;
-    free(g); free(p); free(xt); free(gt); free(q); free(S); free(Y); free(rho); free(alpha); free(fhist);
+    free(g); free(p); free(xt); free(gt); free(q); free(S); free(Y); free(rho); free(alpha); free(fhist); free(ring);
     return 0;
 }
 

@@ -1,0 +1,415 @@
+// ss_api.hip -- the C interface (include/ss.h): contexts, wavevector plans,
+// launch shapes, workspace layout and the energy/gradient driver.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ss.h"
+#include "ss_internal.h"
+
+namespace ss {
+hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab, hipStream_t st);
+hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const double* tab, double* part,
+                     hipStream_t st);
+hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* canon_of_lex, const double* v,
+                             double* nk_out, double* csw, double* blk, double* phi, double* smax, double* kmax,
+                             hipStream_t st);
+hipError_t launch_grad(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
+                       const double* csw, double* gpart, double L, double* grad, hipStream_t st);
+hipError_t launch_weights(const int32_t* n, int64_t M, int d, int64_t R2, int vkind, double* v, hipStream_t st);
+hipError_t enumerate(int d, int64_t R2, int R, hipStream_t st, Plan* pl);
+size_t minimize_extra_bytes(int64_t nv);
+}  // namespace ss
+
+using namespace ss;
+
+namespace {
+
+int set_err(ss_ctx* c, int code, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return code;
+}
+
+int hip_err(ss_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return set_err(c, e == hipErrorOutOfMemory ? SS_ENOMEM : SS_EHIP, m);
+}
+
+#define SS_HIP(ctx, call)                                   \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_err((ctx), e_, #call); \
+  } while (0)
+
+int64_t isqrt64(int64_t x) {
+  int64_t r = (int64_t)sqrt((double)x);
+  while (r * r > x) --r;
+  while ((r + 1) * (r + 1) <= x) ++r;
+  return r;
+}
+
+// |H(R2)| by columns: for each prefix p = (n_1..n_{d-1}) with |p|^2 <= R2 the last
+// component ranges over |n_d| <= r = isqrt(R2 - |p|^2); the half-set rule keeps all
+// of them when the first nonzero prefix component is positive, none when it is
+// negative, and n_d in 1..r when the prefix is zero.
+int64_t count_half(int d, int64_t R2) {
+  const int64_t R = isqrt64(R2);
+  if (d == 1) return R;
+  int64_t total = 0;
+  int64_t p[3] = {-R, -R, -R};
+  const int np = d - 1;
+  for (;;) {
+    int64_t s = 0;
+    int first = 0;
+    for (int a = 0; a < np; ++a) {
+      s += p[a] * p[a];
+      if (!first && p[a] != 0) first = p[a] > 0 ? 1 : -1;
+    }
+    if (s <= R2) {
+      const int64_t r = isqrt64(R2 - s);
+      if (first > 0) total += 2 * r + 1;
+      else if (first == 0) total += r;
+    }
+    int a = np - 1;
+    while (a >= 0 && p[a] == R) p[a--] = -R;
+    if (a < 0) break;
+    ++p[a];
+  }
+  return total;
+}
+
+int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
+  auto key = std::make_pair(d, R2);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    *out = it->second;
+    return SS_OK;
+  }
+  Plan* pl = new (std::nothrow) Plan();
+  if (!pl) return set_err(ctx, SS_ENOMEM, "plan allocation");
+  pl->d = d;
+  pl->R2 = R2;
+  pl->R = (int)isqrt64(R2);
+  SS_HIP(ctx, enumerate(d, R2, pl->R, ctx->build_stream, pl));
+  const int64_t M = pl->M;
+  std::vector<int32_t> lex((size_t)M * d);
+  SS_HIP(ctx, hipMemcpy(lex.data(), pl->lex_n, sizeof(int32_t) * M * d, hipMemcpyDeviceToHost));
+  // runs along the last axis (maximal lexicographic stretches with equal prefix)
+  std::vector<Span> runs;
+  for (int64_t k = 0; k < M; ++k) {
+    bool same = !runs.empty();
+    if (same)
+      for (int a = 0; a < d - 1; ++a)
+        if (lex[k * d + a] != lex[(k - 1) * d + a]) same = false;
+    if (same && lex[k * d + d - 1] != lex[(k - 1) * d + d - 1] + 1) same = false;
+    if (same) {
+      runs.back().len++;
+    } else {
+      Span s{};
+      s.k0 = (int32_t)k;
+      s.len = 1;
+      for (int a = 0; a < d; ++a) s.n[a] = (int16_t)lex[k * d + a];
+      runs.push_back(s);
+    }
+  }
+  // pieces of at most kSegLen, balanced within a run, longest first
+  std::vector<Span> segs;
+  for (const Span& r : runs) {
+    const int pieces = (r.len + kSegLen - 1) / kSegLen;
+    const int base = r.len / pieces, extra = r.len % pieces;
+    int off = 0;
+    for (int i = 0; i < pieces; ++i) {
+      Span s = r;
+      s.k0 = r.k0 + off;
+      s.len = base + (i < extra ? 1 : 0);
+      s.n[d - 1] = (int16_t)(r.n[d - 1] + off);
+      off += s.len;
+      segs.push_back(s);
+    }
+  }
+  std::stable_sort(segs.begin(), segs.end(), [](const Span& a, const Span& b) { return a.len > b.len; });
+  pl->nruns = (int64_t)runs.size();
+  pl->nsegs = (int64_t)segs.size();
+  SS_HIP(ctx, hipMalloc(&pl->runs, sizeof(Span) * runs.size()));
+  SS_HIP(ctx, hipMalloc(&pl->segs, sizeof(Span) * segs.size()));
+  SS_HIP(ctx, hipMemcpy(pl->runs, runs.data(), sizeof(Span) * runs.size(), hipMemcpyHostToDevice));
+  SS_HIP(ctx, hipMemcpy(pl->segs, segs.data(), sizeof(Span) * segs.size(), hipMemcpyHostToDevice));
+  pl->run_len_prefix.assign(runs.size() + 1, 0);
+  for (size_t r = 0; r < runs.size(); ++r) pl->run_len_prefix[r + 1] = pl->run_len_prefix[r] + runs[r].len;
+  ctx->plans[key] = pl;
+  *out = pl;
+  return SS_OK;
+}
+
+// wavevector chunks of about equal pair count for the gradient pass
+int chunk_bounds(ss_ctx* ctx, Plan* pl, int Q, int32_t** out) {
+  auto it = pl->chunk_begin.find(Q);
+  if (it != pl->chunk_begin.end()) {
+    *out = it->second;
+    return SS_OK;
+  }
+  std::vector<int32_t> b(Q + 1);
+  const int64_t total = pl->run_len_prefix.back();
+  size_t r = 0;
+  for (int q = 0; q <= Q; ++q) {
+    const int64_t target = (total * q) / Q;
+    while (r < pl->run_len_prefix.size() - 1 && pl->run_len_prefix[r] < target) ++r;
+    b[q] = (int32_t)r;
+  }
+  b[Q] = (int32_t)pl->nruns;
+  int32_t* dev = nullptr;
+  SS_HIP(ctx, hipMalloc(&dev, sizeof(int32_t) * (Q + 1)));
+  SS_HIP(ctx, hipMemcpy(dev, b.data(), sizeof(int32_t) * (Q + 1), hipMemcpyHostToDevice));
+  pl->chunk_begin[Q] = dev;
+  *out = dev;
+  return SS_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int make_cfg(ss_ctx* ctx, const ss_problem* p, const Plan* pl, LaunchCfg* c) {
+  c->d = p->d;
+  c->N = p->N;
+  c->M = p->M;
+  c->R1 = pl->R + 1;
+  const size_t per_particle = (size_t)p->d * c->R1 * 4 * sizeof(double);
+  const size_t lds_budget = 64 * 1024;
+  if (16 * per_particle <= lds_budget) c->pt = 16;
+  else if (4 * per_particle <= lds_budget) c->pt = 4;
+  else if (per_particle <= lds_budget) c->pt = 1;
+  else return set_err(ctx, SS_EINVAL, "cutoff radius too large for the LDS particle tables");
+  c->segblocks = (pl->nsegs + kThreads - 1) / kThreads;
+  const int64_t target = 2048;
+  int64_t P = (target + c->segblocks - 1) / c->segblocks;
+  const int64_t maxP = (c->N + c->pt - 1) / c->pt;
+  P = std::max<int64_t>(1, std::min(P, maxP));
+  int64_t chunk = (c->N + P - 1) / P;
+  chunk = ((chunk + c->pt - 1) / c->pt) * c->pt;
+  c->chunk = chunk;
+  c->P = (c->N + chunk - 1) / chunk;
+  const int64_t pblocks = (c->N + kThreads - 1) / kThreads;
+  int64_t Q = (target + pblocks - 1) / pblocks;
+  Q = std::max<int64_t>(1, std::min<int64_t>(Q, std::min<int64_t>(pl->nruns, 4096)));
+  c->Q = (int)Q;
+  c->combine_blocks = (c->M + kThreads - 1) / kThreads;
+  size_t off = 0;
+  c->off_tab = off;
+  off += align256((size_t)p->d * c->R1 * 4 * c->N * sizeof(double));
+  c->off_part = off;
+  off += align256((size_t)c->P * 4 * c->M * sizeof(double));
+  c->off_csw = off;
+  off += align256((size_t)4 * c->M * sizeof(double));
+  c->off_gpart = off;
+  off += align256((size_t)c->Q * 2 * p->d * c->N * sizeof(double));
+  c->off_blk = off;
+  off += align256((size_t)c->combine_blocks * 5 * sizeof(double));
+  c->off_scalar = off;
+  off += align256(8 * sizeof(double));
+  c->total = off;
+  return SS_OK;
+}
+
+int check_problem(ss_ctx* ctx, const ss_problem* p) {
+  if (!p) return set_err(ctx, SS_EINVAL, "problem is NULL");
+  if (p->d < 1 || p->d > 4) return set_err(ctx, SS_EINVAL, "d must be in 1..4");
+  if (p->N < 1) return set_err(ctx, SS_EINVAL, "N must be >= 1");
+  if (p->R2 < 1) return set_err(ctx, SS_EINVAL, "R2 must be >= 1");
+  if (!(p->L > 0.0) || !isfinite(p->L)) return set_err(ctx, SS_EINVAL, "L must be positive and finite");
+  if (p->vkind < 0 || p->vkind > 2) return set_err(ctx, SS_EINVAL, "vkind must be 0, 1 or 2");
+  if (isqrt64(p->R2) > 32767) return set_err(ctx, SS_EINVAL, "R2 too large");
+  if (p->N > ((int64_t)1 << 31) / 4) return set_err(ctx, SS_EINVAL, "N too large");
+  const int64_t M = count_half(p->d, p->R2);
+  if (M != p->M) return set_err(ctx, SS_EINVAL, "M does not match |H(R2)|");
+  if (M < 1 || M >= ((int64_t)1 << 31)) return set_err(ctx, SS_EINVAL, "M out of range");
+  return SS_OK;
+}
+
+}  // namespace
+
+namespace ss {
+// shared with the minimiser
+int prepare(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg) {
+  int rc = check_problem(ctx, p);
+  if (rc) return rc;
+  SS_HIP(ctx, hipSetDevice(ctx->device));
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    rc = build_plan(ctx, p->d, p->R2, pl);
+  }
+  if (rc) return rc;
+  return make_cfg(ctx, p, *pl, cfg);
+}
+
+int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg& c, const double* v_dev,
+                     const double* pos, double* phi, double* smax, double* grad, double* nk, char* ws,
+                     hipStream_t st, double* kmax) {
+  double* tab = (double*)(ws + c.off_tab);
+  double* part = (double*)(ws + c.off_part);
+  double* csw = (double*)(ws + c.off_csw);
+  double* gpart = (double*)(ws + c.off_gpart);
+  double* blk = (double*)(ws + c.off_blk);
+  double* scal = (double*)(ws + c.off_scalar);
+  const double* v = p->vkind == 0 ? nullptr : v_dev;
+  SS_HIP(ctx, launch_table(pos, p->d, p->N, c.R1, tab, st));
+  SS_HIP(ctx, launch_nk(c, pl->segs, pl->nsegs, tab, part, st));
+  SS_HIP(ctx, launch_nk_combine(c, part, pl->canon_of_lex, v, nk, csw, blk, phi ? phi : scal,
+                                smax ? smax : scal + 2, kmax, st));
+  if (grad) {
+    int32_t* cb = nullptr;
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      int rc = chunk_bounds(ctx, pl, c.Q, &cb);
+      if (rc) return rc;
+    }
+    SS_HIP(ctx, launch_grad(c, pl->runs, cb, tab, csw, gpart, p->L, grad, st));
+  }
+  return SS_OK;
+}
+}  // namespace ss
+
+extern "C" {
+
+int ss_create(int device, ss_ctx** out) {
+  if (!out) return SS_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SS_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return SS_EHIP;
+  ss_ctx* c = new (std::nothrow) ss_ctx();
+  if (!c) return SS_ENOMEM;
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->build_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return SS_EHIP;
+  }
+  *out = c;
+  return SS_OK;
+}
+
+int ss_destroy(ss_ctx* ctx) {
+  if (!ctx) return SS_OK;
+  hipSetDevice(ctx->device);
+  for (auto& kv : ctx->plans) {
+    Plan* pl = kv.second;
+    hipFree(pl->lex_n);
+    hipFree(pl->canon_n);
+    hipFree(pl->canon_of_lex);
+    hipFree(pl->runs);
+    hipFree(pl->segs);
+    for (auto& cb : pl->chunk_begin) hipFree(cb.second);
+    delete pl;
+  }
+  if (ctx->build_stream) hipStreamDestroy(ctx->build_stream);
+  delete ctx;
+  return SS_OK;
+}
+
+const char* ss_strerror(int code) {
+  switch (code) {
+    case SS_OK: return "ok";
+    case SS_PENDING: return "pending";
+    case SS_EINVAL: return "invalid argument";
+    case SS_ENOMEM: return "out of device memory";
+    case SS_EHIP: return "HIP runtime error";
+    case SS_ENOTFOUND: return "unknown ticket";
+    case SS_ESTATE: return "invalid state";
+    case SS_ENUMERIC: return "non-finite value";
+    default: return "unknown error code";
+  }
+}
+
+const char* ss_last_error(ss_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int ss_count(int d, int64_t R2, int64_t* M) {
+  if (!M || d < 1 || d > 4 || R2 < 1 || isqrt64(R2) > 32767) return SS_EINVAL;
+  *M = count_half(d, R2);
+  return SS_OK;
+}
+
+int ss_cutoff(int d, int64_t N, double chi, int64_t* R2, int64_t* M) {
+  if (!R2 || !M || d < 1 || d > 4 || N < 2 || !(chi > 0.0) || !(chi < 0.5)) return SS_EINVAL;
+  const double T = chi * (double)d * (double)(N - 1);
+  if (count_half(d, 1) > T) return SS_EINVAL;
+  // largest R2 with M(R2) <= T (M is nondecreasing), then down to a realised shell
+  int64_t lo = 1, hi = 2;
+  while (count_half(d, hi) <= T) {
+    lo = hi;
+    hi *= 2;
+    if (hi > ((int64_t)1 << 40)) return SS_EINVAL;
+  }
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (count_half(d, mid) <= T) lo = mid;
+    else hi = mid;
+  }
+  int64_t s = lo;
+  const int64_t Ms = count_half(d, s);
+  while (s > 1 && count_half(d, s - 1) == Ms) --s;
+  *R2 = s;
+  *M = Ms;
+  return SS_OK;
+}
+
+int ss_wavevectors(ss_ctx* ctx, int d, int64_t R2, int32_t* n_dev, int64_t capacity, int64_t* M, void* stream) {
+  if (!ctx || !M) return SS_EINVAL;
+  if (d < 1 || d > 4 || R2 < 1 || isqrt64(R2) > 32767) return set_err(ctx, SS_EINVAL, "bad (d, R2)");
+  SS_HIP(ctx, hipSetDevice(ctx->device));
+  Plan* pl = nullptr;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    int rc = build_plan(ctx, d, R2, &pl);
+    if (rc) return rc;
+  }
+  *M = pl->M;
+  if (!n_dev) return SS_OK;
+  if (capacity < pl->M) return set_err(ctx, SS_EINVAL, "capacity < M");
+  hipStream_t st = (hipStream_t)stream;
+  SS_HIP(ctx, hipMemcpyAsync(n_dev, pl->canon_n, sizeof(int32_t) * pl->M * d, hipMemcpyDeviceToDevice, st));
+  SS_HIP(ctx, hipStreamSynchronize(st));
+  return SS_OK;
+}
+
+int ss_weights(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, double* v_dev, void* stream) {
+  if (!ctx) return SS_EINVAL;
+  int rc = check_problem(ctx, prob);
+  if (rc) return rc;
+  if (!n_dev || !v_dev) return set_err(ctx, SS_EINVAL, "NULL n_dev or v_dev");
+  if (prob->vkind != 0 && prob->vkind != 1) return set_err(ctx, SS_EINVAL, "ss_weights needs vkind 0 or 1");
+  SS_HIP(ctx, hipSetDevice(ctx->device));
+  SS_HIP(ctx, launch_weights(n_dev, prob->M, prob->d, prob->R2, prob->vkind, v_dev, (hipStream_t)stream));
+  return SS_OK;
+}
+
+int ss_workspace_size(ss_ctx* ctx, const ss_problem* prob, int op, size_t* bytes) {
+  if (!ctx || !bytes) return SS_EINVAL;
+  if (op != 0 && op != 1) return set_err(ctx, SS_EINVAL, "unknown op");
+  Plan* pl = nullptr;
+  LaunchCfg c;
+  int rc = prepare(ctx, prob, &pl, &c);
+  if (rc) return rc;
+  *bytes = c.total + (op == 1 ? minimize_extra_bytes((int64_t)prob->d * prob->N) : 0);
+  return SS_OK;
+}
+
+int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
+                   const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
+                   void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return SS_EINVAL;
+  Plan* pl = nullptr;
+  LaunchCfg c;
+  int rc = prepare(ctx, prob, &pl, &c);
+  if (rc) return rc;
+  if (!n_dev || !pos_dev || !phi_dev || !ws) return set_err(ctx, SS_EINVAL, "NULL required pointer");
+  if (prob->vkind != 0 && !v_dev) return set_err(ctx, SS_EINVAL, "vkind != 0 needs v_dev");
+  if (ws_bytes < c.total) return set_err(ctx, SS_EINVAL, "workspace too small");
+  return energy_grad_impl(ctx, prob, pl, c, v_dev, pos_dev, phi_dev, smax_dev, grad_dev, nk_dev, (char*)ws,
+                          (hipStream_t)stream, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,592 @@
+// ss_kernels.hip -- the double-double hot path on gfx950.
+//
+// Paper: Morse, Kim, Steinhardt, Torquato, "Generating large disordered
+// stealthy hyperuniform systems with ultra-high accuracy ..." (arXiv:2304.09139).
+//
+// The energy needs, for every wavevector k = 2 pi n / L of the half set H and
+// every particle j, the factor exp(i k.r_j) (Eq. ntilde and Eq. force; the
+// "Simulations" paragraph counts both O(MN) sums as the whole cost).  With
+// fractional coordinates u = r / L the factor is a product over axes,
+//     exp(2 pi i n.u_j) = prod_a z_{j,a}^{n_a},   z_{j,a}^m = exp(2 pi i m u_{j,a}),
+// so the kernels never form n.u per pair:
+//   * k_table      builds z_{j,a}^m for m = 0..R by an exact reduction of
+//                  m u mod 1 and a double-double sin/cos (the only
+//                  transcendental work, O(d R N));
+//   * k_nk         runs the n~(k) reduction.  Each lane owns up to kSegLen
+//                  consecutive wavevectors of one column (fixed n_0..n_{d-2})
+//                  and walks them with one complex dd product per pair,
+//                  looping over a particle chunk whose tables are staged in
+//                  LDS;
+//   * k_nk_combine sums the chunk partials in a fixed order with the accurate
+//                  dd addition and forms v C, v S, Phi and S_max per block;
+//   * k_grad       is the transposed gradient pass: each lane owns one particle
+//                  and all lanes walk the same wavevector runs (uniform data),
+//                  one complex product and a dd dot product per pair.
+// All reductions have a fixed order: results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ss_dd.h"
+#include "ss_internal.h"
+
+namespace ss {
+
+// ---------------------------------------------------------------------------
+// table of z^m = exp(2 pi i m u) per particle and axis
+// layout: tab[((a * R1 + m) * 4 + c) * N + j], c = (re.hi, re.lo, im.hi, im.lo)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_table(const double* __restrict__ pos, int d, int64_t N, int R1,
+                                                    double* __restrict__ tab) {
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t total = (int64_t)d * R1 * N;
+  if (idx >= total) return;
+  const int64_t j = idx % N;
+  const int64_t am = idx / N;
+  const int m = (int)(am % R1);
+  const int a = (int)(am / R1);
+  const double uh = pos[(int64_t)a * N + j];
+  const double ul = pos[(int64_t)(d + a) * N + j];
+  const cdd z = expi2pi(phase_of((double)m, uh, ul));
+  const int64_t base = am * 4 * N + j;
+  tab[base] = z.rh;
+  tab[base + N] = z.rl;
+  tab[base + 2 * N] = z.ih;
+  tab[base + 3 * N] = z.il;
+}
+
+// entry z_a^m of the particle table staged in LDS ([a][m][c] per particle),
+// conjugated for negative exponents (z^-m = conj z^m for |z| = 1)
+__device__ __forceinline__ cdd lds_entry(const double* tp, int R1, int a, int m) {
+  const int mm = m < 0 ? -m : m;
+  const double* e = tp + (a * R1 + mm) * 4;
+  cdd z{e[0], e[1], e[2], e[3]};
+  if (m < 0) z = cconj(z);
+  return z;
+}
+
+// ---------------------------------------------------------------------------
+// n~(k) partial sums.  grid = (segment blocks, particle chunks).
+// part[((p * 4) + c) * M + k], c = (C.hi, C.lo, S.hi, S.lo), k in walk order.
+// ---------------------------------------------------------------------------
+template <int D, int PT>
+__global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, int64_t nseg,
+                                                 const double* __restrict__ tab, int64_t N, int R1,
+                                                 int64_t chunk, double* __restrict__ part, int64_t M) {
+  extern __shared__ double lds[];  // [PT][D][R1][4]
+  const int tid = threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * kThreads + tid;
+  const Span sg = segs[s < nseg ? s : nseg - 1];
+  const int len = s < nseg ? sg.len : 0;
+  const int epp = D * R1 * 4;  // doubles per particle
+
+  double crh[kSegLen], crl[kSegLen], cih[kSegLen], cil[kSegLen];
+#pragma unroll
+  for (int t = 0; t < kSegLen; ++t) crh[t] = crl[t] = cih[t] = cil[t] = 0.0;
+
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
+  for (int64_t tile = j0; tile < j1; tile += PT) {
+    const int np = (int)((j1 - tile) < PT ? (j1 - tile) : PT);
+    __syncthreads();
+    for (int i = tid; i < epp * PT; i += kThreads) {
+      const int p = i % PT;
+      const int ec = i / PT;
+      lds[p * epp + ec] = p < np ? tab[(int64_t)ec * N + tile + p] : 0.0;
+    }
+    __syncthreads();
+    if (len > 0) {
+      for (int p = 0; p < np; ++p) {
+        const double* tp = lds + p * epp;
+        cdd w = lds_entry(tp, R1, D - 1, sg.n[D - 1]);
+#pragma unroll
+        for (int a = 0; a < D - 1; ++a) w = cmul(w, lds_entry(tp, R1, a, sg.n[a]));
+        const cdd z = lds_entry(tp, R1, D - 1, 1);
+#pragma unroll
+        for (int t = 0; t < kSegLen; ++t) {
+          if (t < len) {
+            lazy_acc(crh[t], crl[t], w.rh, w.rl);
+            lazy_acc(cih[t], cil[t], w.ih, w.il);
+            if (t + 1 < len) w = cmul(w, z);
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kSegLen; ++t) {
+        renorm(crh[t], crl[t]);
+        renorm(cih[t], cil[t]);
+      }
+    }
+  }
+  double* out = part + (int64_t)blockIdx.y * 4 * M;
+#pragma unroll
+  for (int t = 0; t < kSegLen; ++t) {
+    if (t < len) {
+      const int64_t k = sg.k0 + t;
+      out[k] = crh[t];
+      out[M + k] = crl[t];
+      out[2 * M + k] = cih[t];
+      out[3 * M + k] = cil[t];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// combine the P chunk partials per wavevector (fixed order, accurate dd sums);
+// write n~ in canonical order, (v C, v S) in walk order, and per-block Phi and
+// S_max partials.  blk[b * 5 + (0..4)] = Phi.hi, Phi.lo, Smax.hi, Smax.lo, kmax
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restrict__ part, int64_t P, int64_t M,
+                                                         int64_t N, const int32_t* __restrict__ canon_of_lex,
+                                                         const double* __restrict__ v, double* __restrict__ nk_out,
+                                                         double* __restrict__ csw, double* __restrict__ blk) {
+  __shared__ double s_ph[kThreads], s_pl[kThreads], s_mh[kThreads], s_ml[kThreads];
+  __shared__ int64_t s_mk[kThreads];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + tid;
+  dd phi{0.0, 0.0}, sk{-1.0, 0.0};
+  int64_t kc = INT64_MAX;
+  if (i < M) {
+    dd C{0.0, 0.0}, S{0.0, 0.0};
+    for (int64_t p = 0; p < P; ++p) {
+      const double* q = part + p * 4 * M;
+      C = dd_add(C, dd{q[i], q[M + i]});
+      S = dd_add(S, dd{q[2 * M + i], q[3 * M + i]});
+    }
+    kc = canon_of_lex[i];
+    if (nk_out) {
+      nk_out[kc] = C.h;
+      nk_out[M + kc] = C.l;
+      nk_out[2 * M + kc] = S.h;
+      nk_out[3 * M + kc] = S.l;
+    }
+    const dd w = v ? dd{v[kc], v[M + kc]} : dd{1.0, 0.0};
+    const dd Cw = v ? dd_mul(w, C) : C;
+    const dd Sw = v ? dd_mul(w, S) : S;
+    csw[i] = Cw.h;
+    csw[M + i] = Cw.l;
+    csw[2 * M + i] = Sw.h;
+    csw[3 * M + i] = Sw.l;
+    const dd mag = dd_add(dd_mul(C, C), dd_mul(S, S));
+    phi = v ? dd_mul(w, mag) : mag;
+    sk = dd_div_d(mag, (double)N);
+  }
+  s_ph[tid] = phi.h;
+  s_pl[tid] = phi.l;
+  s_mh[tid] = sk.h;
+  s_ml[tid] = sk.l;
+  s_mk[tid] = kc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      const dd a = dd_add(dd{s_ph[tid], s_pl[tid]}, dd{s_ph[tid + w], s_pl[tid + w]});
+      s_ph[tid] = a.h;
+      s_pl[tid] = a.l;
+      const dd x{s_mh[tid], s_ml[tid]}, y{s_mh[tid + w], s_ml[tid + w]};
+      if (dd_less(x, y) || (!dd_less(y, x) && s_mk[tid + w] < s_mk[tid])) {
+        s_mh[tid] = y.h;
+        s_ml[tid] = y.l;
+        s_mk[tid] = s_mk[tid + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double* b = blk + (int64_t)blockIdx.x * 5;
+    b[0] = s_ph[0];
+    b[1] = s_pl[0];
+    b[2] = s_mh[0];
+    b[3] = s_ml[0];
+    b[4] = (double)s_mk[0];
+  }
+}
+
+// single block: fixed-order reduction of the per-block partials
+__global__ void __launch_bounds__(kThreads) k_final(const double* __restrict__ blk, int64_t nblk,
+                                                    double* __restrict__ phi_out, double* __restrict__ smax_out,
+                                                    double* __restrict__ kmax_out) {
+  __shared__ double s_ph[kThreads], s_pl[kThreads], s_mh[kThreads], s_ml[kThreads], s_mk[kThreads];
+  const int tid = threadIdx.x;
+  dd phi{0.0, 0.0}, sk{-1.0, 0.0};
+  double kk = 1e300;
+  for (int64_t b = tid; b < nblk; b += kThreads) {
+    const double* q = blk + b * 5;
+    phi = dd_add(phi, dd{q[0], q[1]});
+    const dd y{q[2], q[3]};
+    if (dd_less(sk, y) || (!dd_less(y, sk) && q[4] < kk)) {
+      sk = y;
+      kk = q[4];
+    }
+  }
+  s_ph[tid] = phi.h;
+  s_pl[tid] = phi.l;
+  s_mh[tid] = sk.h;
+  s_ml[tid] = sk.l;
+  s_mk[tid] = kk;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      const dd a = dd_add(dd{s_ph[tid], s_pl[tid]}, dd{s_ph[tid + w], s_pl[tid + w]});
+      s_ph[tid] = a.h;
+      s_pl[tid] = a.l;
+      const dd x{s_mh[tid], s_ml[tid]}, y{s_mh[tid + w], s_ml[tid + w]};
+      if (dd_less(x, y) || (!dd_less(y, x) && s_mk[tid + w] < s_mk[tid])) {
+        s_mh[tid] = y.h;
+        s_ml[tid] = y.l;
+        s_mk[tid] = s_mk[tid + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    phi_out[0] = s_ph[0];
+    phi_out[1] = s_pl[0];
+    smax_out[0] = s_mh[0];
+    smax_out[1] = s_ml[0];
+    if (kmax_out) kmax_out[0] = s_mk[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gradient partials.  grid = (particle blocks, wavevector chunks).
+// gpart[((q * 2 + plane) * D + a) * N + j]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ cdd tab_entry(const double* __restrict__ tab, int64_t N, int R1, int a, int m, int64_t j) {
+  const int mm = m < 0 ? -m : m;
+  const double* e = tab + ((int64_t)(a * R1 + mm) * 4) * N + j;
+  cdd z{e[0], e[N], e[2 * N], e[3 * N]};
+  if (m < 0) z = cconj(z);
+  return z;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs,
+                                                   const int32_t* __restrict__ chunk_begin,
+                                                   const double* __restrict__ tab, const double* __restrict__ csw,
+                                                   int64_t N, int R1, int64_t M, double* __restrict__ gpart) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t jj = j < N ? j : N - 1;
+  const int q = blockIdx.y;
+  const int r0 = chunk_begin[q], r1 = chunk_begin[q + 1];
+  const cdd z = tab_entry(tab, N, R1, D - 1, 1, jj);
+  double gh[D], gl[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) gh[a] = gl[a] = 0.0;
+
+  for (int r = r0; r < r1; ++r) {
+    const Span run = runs[r];
+    cdd w = tab_entry(tab, N, R1, D - 1, run.n[D - 1], jj);
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) w = cmul(w, tab_entry(tab, N, R1, a, run.n[a], jj));
+    double q0h = 0.0, q0l = 0.0, qdh = 0.0, qdl = 0.0;
+    double nd = (double)run.n[D - 1];
+    const double* cp = csw + run.k0;
+    for (int t = 0; t < run.len; ++t) {
+      const double Ch = cp[t], Cl = cp[M + t], Sh = cp[2 * M + t], Sl = cp[3 * M + t];
+      double qs, qt;
+      lazy_dot2m(Sh, Sl, w.rh, w.rl, Ch, Cl, w.ih, w.il, qs, qt);  // v (S c - C s)
+      lazy_acc(q0h, q0l, qs, qt);
+      double p = nd * qs;
+      double e = __builtin_fma(nd, qs, -p);
+      e = __builtin_fma(nd, qt, e);
+      lazy_acc(qdh, qdl, p, e);
+      nd += 1.0;
+      w = cmul(w, z);
+    }
+    renorm(q0h, q0l);
+    renorm(qdh, qdl);
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) {
+      const double na = (double)run.n[a];
+      double p = na * q0h;
+      double e = __builtin_fma(na, q0h, -p);
+      e = __builtin_fma(na, q0l, e);
+      lazy_acc(gh[a], gl[a], p, e);
+      renorm(gh[a], gl[a]);
+    }
+    lazy_acc(gh[D - 1], gl[D - 1], qdh, qdl);
+    renorm(gh[D - 1], gl[D - 1]);
+  }
+  if (j < N) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      gpart[((int64_t)(q * 2 + 0) * D + a) * N + j] = gh[a];
+      gpart[((int64_t)(q * 2 + 1) * D + a) * N + j] = gl[a];
+    }
+  }
+}
+
+// sum the Q gradient partials (fixed order) and scale by 4 pi / L:
+// dPhi/dr_{j,a} = (4 pi / L) sum_k v_k n_{k,a} (S_k c_jk - C_k s_jk)
+__global__ void __launch_bounds__(kThreads) k_grad_combine(const double* __restrict__ gpart, int Q, int d, int64_t N,
+                                                           double L, double* __restrict__ grad) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // a * N + j
+  const int64_t DN = (int64_t)d * N;
+  if (i >= DN) return;
+  dd g{0.0, 0.0};
+  for (int q = 0; q < Q; ++q) g = dd_add(g, dd{gpart[(int64_t)(q * 2) * DN + i], gpart[(int64_t)(q * 2 + 1) * DN + i]});
+  const dd tp = two_pi_dd();
+  const dd scale = dd_div_d(dd{2.0 * tp.h, 2.0 * tp.l}, L);
+  g = dd_mul(g, scale);
+  grad[i] = g.h;
+  grad[DN + i] = g.l;
+}
+
+// ---------------------------------------------------------------------------
+// wavevector enumeration (integer, bit-exact)
+// candidates are the lexicographically ordered grid [-R, R]^d
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool candidate(int64_t idx, int d, int R, int64_t R2, int32_t* n, int64_t* shell) {
+  const int64_t side = 2 * R + 1;
+  int64_t rem = idx, s = 0;
+  for (int a = d - 1; a >= 0; --a) {
+    n[a] = (int32_t)(rem % side) - R;
+    rem /= side;
+  }
+  int first = 0;
+  for (int a = 0; a < d; ++a) {
+    s += (int64_t)n[a] * n[a];
+    if (first == 0 && n[a] != 0) first = n[a] > 0 ? 1 : -1;
+  }
+  *shell = s;
+  return s <= R2 && first > 0;  // half set: first nonzero component positive
+}
+
+constexpr int kEnumPer = 1024;  // candidates per block
+
+__global__ void __launch_bounds__(kThreads) k_enum_count(int64_t total, int d, int R, int64_t R2,
+                                                         int32_t* __restrict__ bcount) {
+  __shared__ int s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  int c = 0;
+  int32_t n[4];
+  int64_t sh;
+  const int64_t base = (int64_t)blockIdx.x * kEnumPer;
+  for (int i = threadIdx.x; i < kEnumPer; i += kThreads) {
+    const int64_t idx = base + i;
+    if (idx < total && candidate(idx, d, R, R2, n, &sh)) ++c;
+  }
+  atomicAdd(&s_cnt, c);  // integer: order-independent
+  __syncthreads();
+  if (threadIdx.x == 0) bcount[blockIdx.x] = s_cnt;
+}
+
+__global__ void k_enum_scan(const int32_t* __restrict__ bcount, int64_t nb, int32_t* __restrict__ bofs,
+                            int64_t* __restrict__ total_out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      bofs[b] = (int32_t)acc;
+      acc += bcount[b];
+    }
+    *total_out = acc;
+  }
+}
+
+// stable scatter in lexicographic order; key = (|n|^2 << 32) | lex position
+__global__ void __launch_bounds__(kThreads) k_enum_scatter(int64_t total, int d, int R, int64_t R2,
+                                                           const int32_t* __restrict__ bofs,
+                                                           int32_t* __restrict__ lex_n, uint64_t* __restrict__ keys) {
+  __shared__ int s_flag[kEnumPer];
+  __shared__ int s_pos[kEnumPer];
+  const int64_t base = (int64_t)blockIdx.x * kEnumPer;
+  int32_t n[4];
+  int64_t sh;
+  for (int i = threadIdx.x; i < kEnumPer; i += kThreads) {
+    const int64_t idx = base + i;
+    s_flag[i] = (idx < total && candidate(idx, d, R, R2, n, &sh)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // exclusive scan of the block's flags (1024 entries)
+    int acc = 0;
+    for (int i = 0; i < kEnumPer; ++i) {
+      s_pos[i] = acc;
+      acc += s_flag[i];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kEnumPer; i += kThreads) {
+    if (!s_flag[i]) continue;
+    const int64_t idx = base + i;
+    candidate(idx, d, R, R2, n, &sh);
+    const int64_t pos = (int64_t)bofs[blockIdx.x] + s_pos[i];
+    for (int a = 0; a < d; ++a) lex_n[pos * d + a] = n[a];
+    keys[pos] = ((uint64_t)sh << 32) | (uint64_t)pos;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_fill_keys(uint64_t* __restrict__ keys, int64_t from, int64_t to) {
+  const int64_t i = from + (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < to) keys[i] = ~(uint64_t)0;
+}
+
+// one compare-exchange stage of a bitonic sort (keys are unique)
+__global__ void __launch_bounds__(kThreads) k_bitonic(uint64_t* __restrict__ keys, int64_t n, int64_t j, int64_t k) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int64_t l = i ^ j;
+  if (l > i) {
+    const uint64_t a = keys[i], b = keys[l];
+    const bool up = (i & k) == 0;
+    if ((up && a > b) || (!up && a < b)) {
+      keys[i] = b;
+      keys[l] = a;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_enum_canon(const uint64_t* __restrict__ keys, int64_t M, int d,
+                                                         const int32_t* __restrict__ lex_n,
+                                                         int32_t* __restrict__ canon_n,
+                                                         int32_t* __restrict__ canon_of_lex) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= M) return;
+  const int64_t lp = (int64_t)(keys[i] & 0xffffffffull);
+  for (int a = 0; a < d; ++a) canon_n[i * d + a] = lex_n[lp * d + a];
+  canon_of_lex[lp] = (int32_t)i;
+}
+
+// v_k = (1 - |k|/K)^2 with K^2 = (R2 + 1/2)(2 pi/L)^2, written without
+// cancellation as ((K^2 - |n|^2) / (K^2 (1 + |n|/K)))^2 in units of (2 pi/L)
+__global__ void __launch_bounds__(kThreads) k_weights(const int32_t* __restrict__ n, int64_t M, int d, int64_t R2,
+                                                      int vkind, double* __restrict__ v) {
+  const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= M) return;
+  dd w{1.0, 0.0};
+  if (vkind == 1) {
+    int64_t s = 0;
+    for (int a = 0; a < d; ++a) s += (int64_t)n[k * d + a] * n[k * d + a];
+    const double K2 = (double)R2 + 0.5;
+    const dd root = dd_sqrt(dd_div(dd{(double)s, 0.0}, dd{K2, 0.0}));
+    const dd den = dd_mul_d(dd_add(dd{1.0, 0.0}, root), K2);
+    const dd om = dd_div(dd{K2 - (double)s, 0.0}, den);
+    w = dd_mul(om, om);
+  }
+  v[k] = w.h;
+  v[M + k] = w.l;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers
+// ---------------------------------------------------------------------------
+hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab, hipStream_t st) {
+  const int64_t total = (int64_t)d * R1 * N;
+  const int64_t blocks = (total + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_table, dim3((unsigned)blocks), dim3(kThreads), 0, st, pos, d, N, R1, tab);
+  return hipGetLastError();
+}
+
+template <int D, int PT>
+static hipError_t launch_nk_t(const LaunchCfg& c, const Span* segs, int64_t nseg, const double* tab, double* part,
+                              hipStream_t st) {
+  const size_t lds = (size_t)PT * D * c.R1 * 4 * sizeof(double);
+  hipLaunchKernelGGL((k_nk<D, PT>), dim3((unsigned)c.segblocks, (unsigned)c.P), dim3(kThreads), lds, st, segs,
+                     nseg, tab, c.N, c.R1, c.chunk, part, c.M);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_nk_d(const LaunchCfg& c, const Span* segs, int64_t nseg, const double* tab, double* part,
+                              hipStream_t st) {
+  switch (c.pt) {
+    case 16: return launch_nk_t<D, 16>(c, segs, nseg, tab, part, st);
+    case 4: return launch_nk_t<D, 4>(c, segs, nseg, tab, part, st);
+    default: return launch_nk_t<D, 1>(c, segs, nseg, tab, part, st);
+  }
+}
+
+hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const double* tab, double* part,
+                     hipStream_t st) {
+  switch (c.d) {
+    case 1: return launch_nk_d<1>(c, segs, nseg, tab, part, st);
+    case 2: return launch_nk_d<2>(c, segs, nseg, tab, part, st);
+    case 3: return launch_nk_d<3>(c, segs, nseg, tab, part, st);
+    default: return launch_nk_d<4>(c, segs, nseg, tab, part, st);
+  }
+}
+
+hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* canon_of_lex, const double* v,
+                             double* nk_out, double* csw, double* blk, double* phi, double* smax, double* kmax,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_nk_combine, dim3((unsigned)c.combine_blocks), dim3(kThreads), 0, st, part, c.P, c.M, c.N,
+                     canon_of_lex, v, nk_out, csw, blk);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kThreads), 0, st, blk, c.combine_blocks, phi, smax, kmax);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_grad_d(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
+                                const double* csw, double* gpart, hipStream_t st) {
+  const int64_t blocks = (c.N + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL((k_grad<D>), dim3((unsigned)blocks, (unsigned)c.Q), dim3(kThreads), 0, st, runs, chunk_begin,
+                     tab, csw, c.N, c.R1, c.M, gpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
+                       const double* csw, double* gpart, double L, double* grad, hipStream_t st) {
+  hipError_t e;
+  switch (c.d) {
+    case 1: e = launch_grad_d<1>(c, runs, chunk_begin, tab, csw, gpart, st); break;
+    case 2: e = launch_grad_d<2>(c, runs, chunk_begin, tab, csw, gpart, st); break;
+    case 3: e = launch_grad_d<3>(c, runs, chunk_begin, tab, csw, gpart, st); break;
+    default: e = launch_grad_d<4>(c, runs, chunk_begin, tab, csw, gpart, st); break;
+  }
+  if (e != hipSuccess) return e;
+  const int64_t DN = (int64_t)c.d * c.N;
+  hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((DN + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, gpart,
+                     c.Q, c.d, c.N, L, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights(const int32_t* n, int64_t M, int d, int64_t R2, int vkind, double* v, hipStream_t st) {
+  hipLaunchKernelGGL(k_weights, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, n, M, d, R2,
+                     vkind, v);
+  return hipGetLastError();
+}
+
+// Enumerate H(R2): lexicographic list + canonical list + lex -> canonical map.
+// Device buffers are allocated here; M is returned (a synchronising call).
+hipError_t enumerate(int d, int64_t R2, int R, hipStream_t st, Plan* pl) {
+  int64_t side = 2 * R + 1, total = 1;
+  for (int a = 0; a < d; ++a) total *= side;
+  const int64_t nb = (total + kEnumPer - 1) / kEnumPer;
+  int32_t *bcount = nullptr, *bofs = nullptr;
+  int64_t* dM = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc(&bcount, sizeof(int32_t) * nb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&bofs, sizeof(int32_t) * nb)) != hipSuccess) return e;
+  if ((e = hipMalloc(&dM, sizeof(int64_t))) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_enum_count, dim3((unsigned)nb), dim3(kThreads), 0, st, total, d, R, R2, bcount);
+  hipLaunchKernelGGL(k_enum_scan, dim3(1), dim3(1), 0, st, bcount, nb, bofs, dM);
+  int64_t M = 0;
+  if ((e = hipMemcpyAsync(&M, dM, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  pl->M = M;
+  int64_t P2 = 1;
+  while (P2 < M) P2 <<= 1;
+  uint64_t* keys = nullptr;
+  if ((e = hipMalloc(&keys, sizeof(uint64_t) * P2)) != hipSuccess) return e;
+  if ((e = hipMalloc(&pl->lex_n, sizeof(int32_t) * M * d)) != hipSuccess) return e;
+  if ((e = hipMalloc(&pl->canon_n, sizeof(int32_t) * M * d)) != hipSuccess) return e;
+  if ((e = hipMalloc(&pl->canon_of_lex, sizeof(int32_t) * M)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_enum_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, total, d, R, R2, bofs, pl->lex_n,
+                     keys);
+  if (P2 > M)
+    hipLaunchKernelGGL(k_fill_keys, dim3((unsigned)((P2 - M + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                       keys, M, P2);
+  const unsigned sb = (unsigned)((P2 + kThreads - 1) / kThreads);
+  for (int64_t k = 2; k <= P2; k <<= 1)
+    for (int64_t j = k >> 1; j > 0; j >>= 1) hipLaunchKernelGGL(k_bitonic, dim3(sb), dim3(kThreads), 0, st, keys, P2, j, k);
+  hipLaunchKernelGGL(k_enum_canon, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, keys, M, d,
+                     pl->lex_n, pl->canon_n, pl->canon_of_lex);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  hipFree(keys);
+  hipFree(bcount);
+  hipFree(bofs);
+  hipFree(dM);
+  return hipSuccess;
+}
+
+}  // namespace ss

@@ -1,0 +1,63 @@
+"""The C-ABI library loads on the CPU and exports every symbol include/ss.h declares;
+its host-only entry points (ss_count, ss_cutoff) agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2304_09139_amd import ss
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "ss.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ss_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ss.lib()
+    names = declared_symbols()
+    assert "ss_energy_grad" in names and "ss_wavevectors" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding knows every declared symbol
+    assert set(names) <= set(ss.SIGNATURES)
+
+
+def test_strerror():
+    assert ss.strerror(0) == "ok"
+    assert ss.strerror(-1) == "invalid argument"
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_count_matches_oracle(d):
+    for R2 in list(range(1, 60)) + [97, 298, 721]:
+        if d == 4 and R2 > 300:
+            continue
+        assert ss.count(d, R2) == O.count(d, R2)
+
+
+def test_cutoff_matches_oracle():
+    rng = np.random.default_rng(11)
+    cases = [(2, 128, 0.4), (3, 8000, 0.45), (3, 30000, 0.45), (2, 500, 0.2), (3, 5000, 0.45)]
+    for _ in range(40):
+        d = int(rng.integers(1, 5))
+        N = int(rng.integers(10, 3000))
+        chi = float(rng.uniform(0.02, 0.49))
+        if chi * d * (N - 1) >= 1:
+            cases.append((d, N, chi))
+    for d, N, chi in cases:
+        assert ss.cutoff(d, N, chi) == O.cutoff(d, N, chi), (d, N, chi)
+
+
+def test_host_entry_points_reject_invalid():
+    for args in [(0, 100, 0.3), (5, 100, 0.3), (2, 1, 0.3), (2, 100, 0.5), (2, 100, 0.0), (2, 3, 0.1)]:
+        with pytest.raises(ss.SSError) as e:
+            ss.cutoff(*args)
+        assert e.value.code == ss.SS_EINVAL
+    with pytest.raises(ss.SSError):
+        ss.count(2, 0)
