@@ -1,0 +1,217 @@
+"""Benchmark of the double-double stealthy-hyperuniform hot path on one MI355X.
+
+A step is one whole pass of the path over one synthetic configuration: the
+cutoff from chi, the wavevector set, and an L-BFGS quench of a fresh seeded
+uniform-random start (the paper's Poisson initial condition) until
+S_max <= 1e-40, every energy evaluation being Phi + gradient over all
+particle-wavevector pairs in double-double.  The default workload is d = 3,
+N = 8000, chi = 0.45 (R2 = 297, M = 10779), v(k) = 1.
+
+Printed (one JSON line): dd pair-evaluations per second over the timed steps
+(M N per Phi + gradient evaluation), configs/s at the stated floor, the
+roofline of the dominant kernel (gradient pass) measured with HIP events on
+its launch stream, and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOOR = 1e-40
+# FP64 operations (add, mul, fma each counted once) per particle-wavevector pair
+# in the inner loops, counted from the kernel source: the n~(k) pass does one
+# lazy complex dd product (2 x 16) and two lazy dd accumulations (2 x 8); the
+# gradient pass does the complex product (32), v (S c - C s) (16), two lazy
+# accumulations (2 x 8), n_d q (3) and the exponent step (1).
+OPS_PER_PAIR = {"nk": 48, "grad": 68}
+# MI355X: 256 CUs x 64 FP64 lanes x 2.4 GHz, one FP64 VALU op per lane per clock
+PEAK_FP64_OPS = 256 * 64 * 2.4e9
+WORKLOADS = {
+    "d3_N8000_chi0.45": dict(d=3, N=8000, chi=0.45, cfg_id=2),
+    "d3_N30000_chi0.45": dict(d=3, N=30000, chi=0.45, cfg_id=4),
+    "d2_N128_chi0.4": dict(d=2, N=128, chi=0.4, cfg_id=1),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("ss_dd.h", "ss_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2304_09139_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str) -> float | None:
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when there is none or it was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                key, val = line.split(":", 1)
+                rec[key.strip()] = val.strip()
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(d, N, chi, cfg_id):
+    """The oracle (plain double-double C, all host cores) on a bounded sample of the
+    workload: the n~ pass over a slice of the wavevectors and the gradient pass over a
+    slice of the particles; the rate is pairs per second for both passes together."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2304_09139_amd import inputs
+
+    R2, M = O.cutoff(d, N, chi)
+    n = O.wavevectors(d, R2)
+    pos = inputs.config_positions(cfg_id, d, N, 0)
+    threads = O.num_threads()
+    k_s = max(1, min(M, int(8.0e7 / N)))           # pass-1 sample: k_s x N pairs
+    t = time.perf_counter()
+    nkv = O.nk(n, pos, 0, k_s)
+    t1 = time.perf_counter() - t
+    j_s = max(1, min(N, int(8.0e7 / M)))           # pass-2 sample: j_s x M pairs
+    t = time.perf_counter()
+    O.grad(n, None, pos, nkv, js=np.arange(j_s))
+    t2 = time.perf_counter() - t
+    per_pair = t1 / (k_s * N) + t2 / (j_s * M)     # seconds per pair, both passes
+    return {"value": 1.0 / per_pair, "unit": "dd pairs/s (Phi+grad)", "cores": threads, "kind": "oracle",
+            "sample": f"n~ pass over {k_s} of {M} wavevectors x all {N} particles ({t1:.1f} s) and gradient "
+                      f"pass over {j_s} of {N} particles x all {M} wavevectors ({t2:.1f} s), seed 0"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="d3_N8000_chi0.45", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--evals", type=int, default=0,
+                    help="instead of quenches, run this many Phi + gradient evaluations of the first start and "
+                         "then one 1 GiB device copy (the calibration kernel for the HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU: this build measures the single-GPU hot path; "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2304_09139_amd import inputs, ss
+
+    wl = WORKLOADS[args.workload]
+    d, N, chi = wl["d"], wl["N"], wl["chi"]
+    ctx = ss.Context(0)
+    w = ss.Workload.from_chi(d, N, chi)
+    n = ctx.wavevectors(d, w.R2)
+    # all starting configurations resident in HBM before the timed region
+    starts = [torch.from_numpy(inputs.config_positions(wl["cfg_id"], d, N, r)).cuda()
+              for r in range(args.warmup + args.steps)]
+    ctx.workspace(w, 1)
+    torch.cuda.synchronize()
+    if args.evals > 0:
+        out = ctx.energy_grad(w, n, None, starts[0], grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.evals):
+            ctx.energy_grad(w, n, None, starts[0], grad=True, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        evict = torch.full((1 << 29,), 3, dtype=torch.uint8, device="cuda")  # > the 256 MB MALL
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        del evict
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "evals", "evals": args.evals, "ms_per_eval": dt / args.evals * 1e3,
+                          "pairs_per_s": w.M * N * args.evals / dt, "copy_bytes": src.numel()}), flush=True)
+        ctx.close()
+        return
+    for r in range(args.warmup):
+        ctx.minimize(w, n, None, starts[r], s_floor=FLOOR)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for k in ("nk", "grad", "table"):
+        ctx.profile_read(k, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for r in range(args.warmup, args.warmup + args.steps):
+        results.append(ctx.minimize(w, n, None, starts[r], s_floor=FLOOR))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {k: ctx.profile_read(k, reset=True) for k in ("nk", "grad", "table")}
+    ctx.profile(False)
+
+    evals = sum(r["evals"] for r in results)
+    pairs = w.M * N * evals
+    value = pairs / elapsed
+    converged = sum(1 for r in results if r["status"] == "converged")
+    launches, ms = prof["grad"]
+    avg_s = ms / launches * 1e-3
+    achieved = OPS_PER_PAIR["grad"] * w.M * N / avg_s
+    traffic = read_traffic("k_grad", args.workload)
+    nk_l, nk_ms = prof["nk"]
+    out = {
+        "metric": "dd particle-wavevector pairs/s (Phi+grad) and configs/s at stated max S(k) floor",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "dd",
+        "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
+        "config": {"workload": f"L-BFGS quench to S_max <= {FLOOR:g}, d={d}, N={N}, chi={chi}, v(k)=1",
+                   "d": d, "N": N, "chi": chi, "R2": w.R2, "M": w.M, "s_floor": FLOOR,
+                   "parallelism": "single GPU"},
+        "configs_per_s": converged / elapsed,
+        "converged": f"{converged}/{args.steps}",
+        "smax_worst": max(r["smax"][0] for r in results),
+        "iters_mean": sum(r["iters"] for r in results) / len(results),
+        "evals_mean": evals / len(results),
+        "eval_ms_nk_pass": nk_ms / max(nk_l, 1),
+        "eval_ms_grad_pass": ms / max(launches, 1),
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_grad (gradient pass)",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP64_OPS / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_OPS,
+            "traffic": traffic,
+            "op_count": f"{OPS_PER_PAIR['grad']} FP64 add/mul/fma per pair (each counted once) x M N pairs "
+                        f"per launch; peak = 256 CU x 64 lanes x 2.4 GHz",
+            "launches": launches,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d, N, chi, wl["cfg_id"])
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -14,14 +14,17 @@
 #include "ss_internal.h"
 
 namespace ss {
-hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab, hipStream_t st);
-hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const double* tab, double* part,
-                     hipStream_t st);
-hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* canon_of_lex, const double* v,
-                             double* nk_out, double* csw, double* blk, double* phi, double* smax, double* kmax,
-                             hipStream_t st);
+hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab, hipStream_t st,
+                        const int* active);
+hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units, int64_t nunits,
+                     const double* tab, double* part, hipStream_t st, const int* active);
+hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* rows_of,
+                             const int32_t* canon_of_lex, const double* v, double* nk_out, double* csw, double* blk,
+                             double* phi, double* smax, double* kmax, hipStream_t st, const int* active);
 hipError_t launch_grad(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
-                       const double* csw, double* gpart, double L, double* grad, hipStream_t st);
+                       const double* csw, double* gpart, hipStream_t st, const int* active);
+hipError_t launch_grad_combine(const LaunchCfg& c, const double* gpart, double L, double* grad, hipStream_t st,
+                               const int* active);
 hipError_t launch_weights(const int32_t* n, int64_t M, int d, int64_t R2, int vkind, double* v, hipStream_t st);
 hipError_t enumerate(int d, int64_t R2, int R, hipStream_t st, Plan* pl);
 size_t minimize_extra_bytes(int64_t nv);
@@ -134,8 +137,10 @@ int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
     }
   }
   std::stable_sort(segs.begin(), segs.end(), [](const Span& a, const Span& b) { return a.len > b.len; });
+  for (size_t b = 0; b < segs.size(); b += kNkPieces) pl->block_maxlen.push_back(segs[b].len);
   pl->nruns = (int64_t)runs.size();
   pl->nsegs = (int64_t)segs.size();
+  pl->seg_host = segs;
   SS_HIP(ctx, hipMalloc(&pl->runs, sizeof(Span) * runs.size()));
   SS_HIP(ctx, hipMalloc(&pl->segs, sizeof(Span) * segs.size()));
   SS_HIP(ctx, hipMemcpy(pl->runs, runs.data(), sizeof(Span) * runs.size(), hipMemcpyHostToDevice));
@@ -171,9 +176,60 @@ int chunk_bounds(ss_ctx* ctx, Plan* pl, int Q, int32_t** out) {
   return SS_OK;
 }
 
+// n(k) pass schedule for N particles: piece block b gets P_b particle ranges
+// whose work (longest piece + base cost) x (particles) is about equal across all
+// units, about kTargetBlocks units in total; wavevectors of block b then have P_b
+// partial rows.  Depends only on (d, R2, N).
+constexpr int64_t kTargetBlocks = 2048;     // n(k) pass units (blocks of 4 waves)
+constexpr int64_t kTargetGradBlocks = 2048;  // gradient pass blocks (4 waves each)
+
+int nk_schedule(ss_ctx* ctx, Plan* pl, int64_t N, int pt, Plan::NkSched** out) {
+  auto it = pl->nk_sched.find(N);
+  if (it != pl->nk_sched.end()) {
+    *out = &it->second;
+    return SS_OK;
+  }
+  const size_t nb = pl->block_maxlen.size();
+  double wsum = 0.0;
+  for (int L : pl->block_maxlen) wsum += L + 1.5;
+  std::vector<NkUnit> units;
+  std::vector<int32_t> rows_of(pl->M, 1);
+  int64_t maxrows = 1;
+  for (size_t b = 0; b < nb; ++b) {
+    const double w = pl->block_maxlen[b] + 1.5;
+    int64_t Pb = (int64_t)std::llround((double)kTargetBlocks * w / wsum);
+    Pb = std::max<int64_t>(1, std::min<int64_t>(Pb, (N + pt - 1) / pt));
+    int64_t chunk = (N + Pb - 1) / Pb;
+    chunk = ((chunk + pt - 1) / pt) * pt;
+    Pb = (N + chunk - 1) / chunk;
+    for (int64_t r = 0; r < Pb; ++r) {
+      NkUnit u;
+      u.block = (int32_t)b;
+      u.row = (int32_t)r;
+      u.j0 = (int32_t)(r * chunk);
+      u.j1 = (int32_t)std::min<int64_t>(N, (r + 1) * chunk);
+      units.push_back(u);
+    }
+    maxrows = std::max(maxrows, Pb);
+    const size_t s0 = b * kNkPieces, s1 = std::min(pl->seg_host.size(), s0 + kNkPieces);
+    for (size_t q = s0; q < s1; ++q)
+      for (int t = 0; t < pl->seg_host[q].len; ++t) rows_of[pl->seg_host[q].k0 + t] = (int32_t)Pb;
+  }
+  Plan::NkSched sc;
+  sc.nunits = (int64_t)units.size();
+  sc.rows = maxrows;
+  SS_HIP(ctx, hipMalloc(&sc.units, sizeof(NkUnit) * units.size()));
+  SS_HIP(ctx, hipMalloc(&sc.rows_of, sizeof(int32_t) * rows_of.size()));
+  SS_HIP(ctx, hipMemcpy(sc.units, units.data(), sizeof(NkUnit) * units.size(), hipMemcpyHostToDevice));
+  SS_HIP(ctx, hipMemcpy(sc.rows_of, rows_of.data(), sizeof(int32_t) * rows_of.size(), hipMemcpyHostToDevice));
+  pl->nk_sched[N] = sc;
+  *out = &pl->nk_sched[N];
+  return SS_OK;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int make_cfg(ss_ctx* ctx, const ss_problem* p, const Plan* pl, LaunchCfg* c) {
+int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c) {
   c->d = p->d;
   c->N = p->N;
   c->M = p->M;
@@ -184,20 +240,20 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, const Plan* pl, LaunchCfg* c) {
   else if (4 * per_particle <= lds_budget) c->pt = 4;
   else if (per_particle <= lds_budget) c->pt = 1;
   else return set_err(ctx, SS_EINVAL, "cutoff radius too large for the LDS particle tables");
-  c->segblocks = (pl->nsegs + kThreads - 1) / kThreads;
-  const int64_t target = 2048;
-  int64_t P = (target + c->segblocks - 1) / c->segblocks;
-  const int64_t maxP = (c->N + c->pt - 1) / c->pt;
-  P = std::max<int64_t>(1, std::min(P, maxP));
-  int64_t chunk = (c->N + P - 1) / P;
-  chunk = ((chunk + c->pt - 1) / c->pt) * c->pt;
-  c->chunk = chunk;
-  c->P = (c->N + chunk - 1) / chunk;
-  const int64_t pblocks = (c->N + kThreads - 1) / kThreads;
-  int64_t Q = (target + pblocks - 1) / pblocks;
-  Q = std::max<int64_t>(1, std::min<int64_t>(Q, std::min<int64_t>(pl->nruns, 4096)));
+  c->segblocks = (pl->nsegs + kNkPieces - 1) / kNkPieces;
+  Plan::NkSched* sc = nullptr;
+  {
+    int rc = nk_schedule(ctx, pl, c->N, c->pt, &sc);
+    if (rc) return rc;
+  }
+  c->P = sc->rows;
+  // gradient pass: blocks of 64 particles x Q chunks, each wave of a block on one
+  // of kWaves sub-chunks of equal pair count
+  const int64_t pblocks = (c->N + 63) / 64;
+  int64_t Q = (kTargetGradBlocks + pblocks - 1) / pblocks;
+  Q = std::max<int64_t>(1, std::min<int64_t>(Q, std::min<int64_t>(std::max<int64_t>(1, pl->nruns / kWaves), 1024)));
   c->Q = (int)Q;
-  c->combine_blocks = (c->M + kThreads - 1) / kThreads;
+  c->combine_blocks = (c->M + 63) / 64;
   size_t off = 0;
   c->off_tab = off;
   off += align256((size_t)p->d * c->R1 * 4 * c->N * sizeof(double));
@@ -238,17 +294,39 @@ int prepare(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg) {
   int rc = check_problem(ctx, p);
   if (rc) return rc;
   SS_HIP(ctx, hipSetDevice(ctx->device));
-  {
-    std::lock_guard<std::mutex> g(ctx->mu);
-    rc = build_plan(ctx, p->d, p->R2, pl);
-  }
+  std::lock_guard<std::mutex> g(ctx->mu);
+  rc = build_plan(ctx, p->d, p->R2, pl);
   if (rc) return rc;
   return make_cfg(ctx, p, *pl, cfg);
 }
 
+namespace {
+hipEvent_t prof_event(ss_ctx* ctx) {
+  hipEvent_t e = nullptr;
+  if (!ctx->prof.pool.empty()) {
+    e = ctx->prof.pool.back();
+    ctx->prof.pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+// records an event pair around `launch` on `st` when profiling is enabled
+template <class F>
+hipError_t timed(ss_ctx* ctx, int which, hipStream_t st, F launch) {
+  if (!ctx->prof.enabled) return launch();
+  hipEvent_t a = prof_event(ctx), b = prof_event(ctx);
+  if (a) hipEventRecord(a, st);
+  hipError_t e = launch();
+  if (b) hipEventRecord(b, st);
+  if (a && b) ctx->prof.ev[which].push_back({a, b});
+  return e;
+}
+}  // namespace
+
 int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg& c, const double* v_dev,
                      const double* pos, double* phi, double* smax, double* grad, double* nk, char* ws,
-                     hipStream_t st, double* kmax) {
+                     hipStream_t st, double* kmax, const int* active) {
   double* tab = (double*)(ws + c.off_tab);
   double* part = (double*)(ws + c.off_part);
   double* csw = (double*)(ws + c.off_csw);
@@ -256,18 +334,20 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
   double* blk = (double*)(ws + c.off_blk);
   double* scal = (double*)(ws + c.off_scalar);
   const double* v = p->vkind == 0 ? nullptr : v_dev;
-  SS_HIP(ctx, launch_table(pos, p->d, p->N, c.R1, tab, st));
-  SS_HIP(ctx, launch_nk(c, pl->segs, pl->nsegs, tab, part, st));
-  SS_HIP(ctx, launch_nk_combine(c, part, pl->canon_of_lex, v, nk, csw, blk, phi ? phi : scal,
-                                smax ? smax : scal + 2, kmax, st));
+  SS_HIP(ctx, timed(ctx, 2, st, [&] { return launch_table(pos, p->d, p->N, c.R1, tab, st, active); }));
+  Plan::NkSched* sc = &pl->nk_sched.at(p->N);
+  SS_HIP(ctx, timed(ctx, 0, st, [&] { return launch_nk(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, st, active); }));
+  SS_HIP(ctx, launch_nk_combine(c, part, sc->rows_of, pl->canon_of_lex, v, nk, csw, blk, phi ? phi : scal,
+                                smax ? smax : scal + 2, kmax, st, active));
   if (grad) {
     int32_t* cb = nullptr;
     {
       std::lock_guard<std::mutex> g(ctx->mu);
-      int rc = chunk_bounds(ctx, pl, c.Q, &cb);
+      int rc = chunk_bounds(ctx, pl, c.Q * kWaves, &cb);
       if (rc) return rc;
     }
-    SS_HIP(ctx, launch_grad(c, pl->runs, cb, tab, csw, gpart, p->L, grad, st));
+    SS_HIP(ctx, timed(ctx, 1, st, [&] { return launch_grad(c, pl->runs, cb, tab, csw, gpart, st, active); }));
+    SS_HIP(ctx, launch_grad_combine(c, gpart, p->L, grad, st, active));
   }
   return SS_OK;
 }
@@ -303,8 +383,18 @@ int ss_destroy(ss_ctx* ctx) {
     hipFree(pl->runs);
     hipFree(pl->segs);
     for (auto& cb : pl->chunk_begin) hipFree(cb.second);
+    for (auto& ns : pl->nk_sched) {
+      hipFree(ns.second.units);
+      hipFree(ns.second.rows_of);
+    }
     delete pl;
   }
+  for (auto& v : ctx->prof.ev)
+    for (auto& pr : v) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
   if (ctx->build_stream) hipStreamDestroy(ctx->build_stream);
   delete ctx;
   return SS_OK;
@@ -397,6 +487,36 @@ int ss_workspace_size(ss_ctx* ctx, const ss_problem* prob, int op, size_t* bytes
   return SS_OK;
 }
 
+int ss_profile_enable(ss_ctx* ctx, int enable) {
+  if (!ctx) return SS_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->prof.enabled = enable != 0;
+  return SS_OK;
+}
+
+int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms || kernel < 0 || kernel > 2) return SS_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  auto& v = ctx->prof.ev[kernel];
+  double tot = 0.0;
+  for (auto& pr : v) {
+    SS_HIP(ctx, hipEventSynchronize(pr.second));
+    float ms = 0.0f;
+    SS_HIP(ctx, hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+  }
+  *launches = (int64_t)v.size();
+  *total_ms = tot;
+  if (reset) {
+    for (auto& pr : v) {
+      ctx->prof.pool.push_back(pr.first);
+      ctx->prof.pool.push_back(pr.second);
+    }
+    v.clear();
+  }
+  return SS_OK;
+}
+
 int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
                    const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
                    void* ws, size_t ws_bytes, void* stream) {
@@ -409,7 +529,7 @@ int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, co
   if (prob->vkind != 0 && !v_dev) return set_err(ctx, SS_EINVAL, "vkind != 0 needs v_dev");
   if (ws_bytes < c.total) return set_err(ctx, SS_EINVAL, "workspace too small");
   return energy_grad_impl(ctx, prob, pl, c, v_dev, pos_dev, phi_dev, smax_dev, grad_dev, nk_dev, (char*)ws,
-                          (hipStream_t)stream, nullptr);
+                          (hipStream_t)stream, nullptr, nullptr);
 }
 
 }  // extern "C"

@@ -20,6 +20,14 @@ struct Span {
 };
 static_assert(sizeof(Span) == 16, "Span layout");
 
+// One block of the n(k) pass: piece block `block` over particles [j0, j1),
+// writing partial row `row`.
+struct NkUnit {
+  int32_t block;
+  int32_t row;
+  int32_t j0, j1;
+};
+
 // Everything that depends only on (d, R2): the half set in lexicographic (walk)
 // order and in canonical order, the map between them, the runs along the last
 // axis (gradient pass) and the run pieces of length <= kSegLen (n(k) pass).
@@ -34,7 +42,15 @@ struct Plan {
   Span* segs = nullptr;        // [nsegs] (device), sorted by length, longest first
   int64_t nruns = 0, nsegs = 0;
   std::vector<int64_t> run_len_prefix;           // host, nruns+1
-  std::map<int, int32_t*> chunk_begin;           // Q -> device [Q+1] run boundaries
+  std::vector<int> block_maxlen;                 // host, longest piece of each piece block
+  std::vector<Span> seg_host;                    // host copy of the pieces
+  std::map<int, int32_t*> chunk_begin;           // chunks -> device [chunks+1] run boundaries
+  struct NkSched {
+    NkUnit* units = nullptr;   // device
+    int32_t* rows_of = nullptr;  // device [M]: partial rows per wavevector
+    int64_t nunits = 0, rows = 0;
+  };
+  std::map<int64_t, NkSched> nk_sched;           // N -> n(k) pass schedule
 };
 
 struct LaunchCfg {
@@ -42,8 +58,7 @@ struct LaunchCfg {
   int64_t N, M;
   int R1;          // R + 1 table entries per axis
   int pt;          // particles per LDS tile in the n(k) pass
-  int64_t P;       // particle chunks of the n(k) pass
-  int64_t chunk;   // particles per chunk
+  int64_t P;       // partial rows of the n(k) pass (the most any wavevector has)
   int64_t segblocks;
   int Q;           // wavevector chunks of the gradient pass
   int64_t combine_blocks;
@@ -52,8 +67,19 @@ struct LaunchCfg {
 };
 
 constexpr int kSegLen = 8;        // wavevectors per lane in the n(k) pass
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;     // threads per block
+constexpr int kWaves = 4;         // waves per block
+constexpr int kNkPieces = 256;    // run pieces per n(k) block (one per lane)
 
+}  // namespace ss
+
+namespace ss {
+// optional per-kernel timing: hipEvent pairs recorded on the launch stream
+struct ProfileLog {
+  bool enabled = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];  // 0 n(k) pass, 1 gradient pass, 2 phase table
+  std::vector<hipEvent_t> pool;
+};
 }  // namespace ss
 
 struct ss_ctx {
@@ -62,4 +88,5 @@ struct ss_ctx {
   std::mutex mu;
   std::map<std::pair<int, int64_t>, ss::Plan*> plans;
   hipStream_t build_stream = nullptr;
+  ss::ProfileLog prof;
 };

@@ -36,7 +36,9 @@ namespace ss {
 // layout: tab[((a * R1 + m) * 4 + c) * N + j], c = (re.hi, re.lo, im.hi, im.lo)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_table(const double* __restrict__ pos, int d, int64_t N, int R1,
-                                                    double* __restrict__ tab) {
+                                                    double* __restrict__ tab,
+    const int* __restrict__ active) {
+  if (active && *active == 0) return;
   const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t total = (int64_t)d * R1 * N;
   if (idx >= total) return;
@@ -65,16 +67,22 @@ __device__ __forceinline__ cdd lds_entry(const double* tp, int R1, int a, int m)
 }
 
 // ---------------------------------------------------------------------------
-// n~(k) partial sums.  grid = (segment blocks, particle chunks).
-// part[((p * 4) + c) * M + k], c = (C.hi, C.lo, S.hi, S.lo), k in walk order.
+// n~(k) partial sums.  One block per unit (a block of kNkPieces run pieces, one
+// per lane, over a particle range [j0, j1)); the particle tables of the range are
+// staged through LDS PT particles at a time and every lane walks its piece over
+// every staged particle.
+// part[((row * 4) + c) * M + k], c = (C.hi, C.lo, S.hi, S.lo), k in walk order.
 // ---------------------------------------------------------------------------
 template <int D, int PT>
 __global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, int64_t nseg,
-                                                 const double* __restrict__ tab, int64_t N, int R1,
-                                                 int64_t chunk, double* __restrict__ part, int64_t M) {
+                                                 const NkUnit* __restrict__ units, const double* __restrict__ tab,
+                                                 int64_t N, int R1, double* __restrict__ part, int64_t M,
+    const int* __restrict__ active) {
+  if (active && *active == 0) return;
   extern __shared__ double lds[];  // [PT][D][R1][4]
   const int tid = threadIdx.x;
-  const int64_t s = (int64_t)blockIdx.x * kThreads + tid;
+  const NkUnit u = units[blockIdx.x];
+  const int64_t s = (int64_t)u.block * kNkPieces + tid;
   const Span sg = segs[s < nseg ? s : nseg - 1];
   const int len = s < nseg ? sg.len : 0;
   const int epp = D * R1 * 4;  // doubles per particle
@@ -83,8 +91,8 @@ __global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, 
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) crh[t] = crl[t] = cih[t] = cil[t] = 0.0;
 
-  const int64_t j0 = (int64_t)blockIdx.y * chunk;
-  const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
+  const int64_t j0 = u.j0;
+  const int64_t j1 = u.j1;
   for (int64_t tile = j0; tile < j1; tile += PT) {
     const int np = (int)((j1 - tile) < PT ? (j1 - tile) : PT);
     __syncthreads();
@@ -117,7 +125,7 @@ __global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, 
       }
     }
   }
-  double* out = part + (int64_t)blockIdx.y * 4 * M;
+  double* out = part + (int64_t)u.row * 4 * M;
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) {
     if (t < len) {
@@ -135,48 +143,69 @@ __global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, 
 // write n~ in canonical order, (v C, v S) in walk order, and per-block Phi and
 // S_max partials.  blk[b * 5 + (0..4)] = Phi.hi, Phi.lo, Smax.hi, Smax.lo, kmax
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restrict__ part, int64_t P, int64_t M,
+__global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restrict__ part,
+                                                         const int32_t* __restrict__ rows_of, int64_t M,
                                                          int64_t N, const int32_t* __restrict__ canon_of_lex,
                                                          const double* __restrict__ v, double* __restrict__ nk_out,
-                                                         double* __restrict__ csw, double* __restrict__ blk) {
-  __shared__ double s_ph[kThreads], s_pl[kThreads], s_mh[kThreads], s_ml[kThreads];
-  __shared__ int64_t s_mk[kThreads];
-  const int tid = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + tid;
-  dd phi{0.0, 0.0}, sk{-1.0, 0.0};
-  int64_t kc = INT64_MAX;
+                                                         double* __restrict__ csw, double* __restrict__ blk,
+    const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  // thread (q, g): wavevector i = block * 64 + q, partial group g sums p = g, g+4, ...
+  __shared__ double s_c[kWaves][4][64];
+  __shared__ double s_ph[64], s_pl[64], s_mh[64], s_ml[64];
+  __shared__ int64_t s_mk[64];
+  const int tid = threadIdx.x, q = tid & 63, g = tid >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + q;
+  dd C{0.0, 0.0}, S{0.0, 0.0};
   if (i < M) {
-    dd C{0.0, 0.0}, S{0.0, 0.0};
-    for (int64_t p = 0; p < P; ++p) {
-      const double* q = part + p * 4 * M;
-      C = dd_add(C, dd{q[i], q[M + i]});
-      S = dd_add(S, dd{q[2 * M + i], q[3 * M + i]});
+    const int64_t P = rows_of[i];
+    for (int64_t p = g; p < P; p += kWaves) {
+      const double* r = part + p * 4 * M;
+      C = dd_add(C, dd{r[i], r[M + i]});
+      S = dd_add(S, dd{r[2 * M + i], r[3 * M + i]});
     }
-    kc = canon_of_lex[i];
-    if (nk_out) {
-      nk_out[kc] = C.h;
-      nk_out[M + kc] = C.l;
-      nk_out[2 * M + kc] = S.h;
-      nk_out[3 * M + kc] = S.l;
-    }
-    const dd w = v ? dd{v[kc], v[M + kc]} : dd{1.0, 0.0};
-    const dd Cw = v ? dd_mul(w, C) : C;
-    const dd Sw = v ? dd_mul(w, S) : S;
-    csw[i] = Cw.h;
-    csw[M + i] = Cw.l;
-    csw[2 * M + i] = Sw.h;
-    csw[3 * M + i] = Sw.l;
-    const dd mag = dd_add(dd_mul(C, C), dd_mul(S, S));
-    phi = v ? dd_mul(w, mag) : mag;
-    sk = dd_div_d(mag, (double)N);
   }
-  s_ph[tid] = phi.h;
-  s_pl[tid] = phi.l;
-  s_mh[tid] = sk.h;
-  s_ml[tid] = sk.l;
-  s_mk[tid] = kc;
+  s_c[g][0][q] = C.h;
+  s_c[g][1][q] = C.l;
+  s_c[g][2][q] = S.h;
+  s_c[g][3][q] = S.l;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
+  if (g == 0) {  // ((g0 + g2) + (g1 + g3))
+    dd c02 = dd_add(dd{s_c[0][0][q], s_c[0][1][q]}, dd{s_c[2][0][q], s_c[2][1][q]});
+    dd c13 = dd_add(dd{s_c[1][0][q], s_c[1][1][q]}, dd{s_c[3][0][q], s_c[3][1][q]});
+    dd s02 = dd_add(dd{s_c[0][2][q], s_c[0][3][q]}, dd{s_c[2][2][q], s_c[2][3][q]});
+    dd s13 = dd_add(dd{s_c[1][2][q], s_c[1][3][q]}, dd{s_c[3][2][q], s_c[3][3][q]});
+    C = dd_add(c02, c13);
+    S = dd_add(s02, s13);
+    dd phi{0.0, 0.0}, sk{-1.0, 0.0};
+    int64_t kc = INT64_MAX;
+    if (i < M) {
+      kc = canon_of_lex[i];
+      if (nk_out) {
+        nk_out[kc] = C.h;
+        nk_out[M + kc] = C.l;
+        nk_out[2 * M + kc] = S.h;
+        nk_out[3 * M + kc] = S.l;
+      }
+      const dd w = v ? dd{v[kc], v[M + kc]} : dd{1.0, 0.0};
+      const dd Cw = v ? dd_mul(w, C) : C;
+      const dd Sw = v ? dd_mul(w, S) : S;
+      csw[i] = Cw.h;
+      csw[M + i] = Cw.l;
+      csw[2 * M + i] = Sw.h;
+      csw[3 * M + i] = Sw.l;
+      const dd mag = dd_add(dd_mul(C, C), dd_mul(S, S));
+      phi = v ? dd_mul(w, mag) : mag;
+      sk = dd_div_d(mag, (double)N);
+    }
+    s_ph[q] = phi.h;
+    s_pl[q] = phi.l;
+    s_mh[q] = sk.h;
+    s_ml[q] = sk.l;
+    s_mk[q] = kc;
+  }
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
     if (tid < w) {
       const dd a = dd_add(dd{s_ph[tid], s_pl[tid]}, dd{s_ph[tid + w], s_pl[tid + w]});
       s_ph[tid] = a.h;
@@ -203,7 +232,9 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restric
 // single block: fixed-order reduction of the per-block partials
 __global__ void __launch_bounds__(kThreads) k_final(const double* __restrict__ blk, int64_t nblk,
                                                     double* __restrict__ phi_out, double* __restrict__ smax_out,
-                                                    double* __restrict__ kmax_out) {
+                                                    double* __restrict__ kmax_out,
+    const int* __restrict__ active) {
+  if (active && *active == 0) return;
   __shared__ double s_ph[kThreads], s_pl[kThreads], s_mh[kThreads], s_ml[kThreads], s_mk[kThreads];
   const int tid = threadIdx.x;
   dd phi{0.0, 0.0}, sk{-1.0, 0.0};
@@ -262,11 +293,15 @@ template <int D>
 __global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs,
                                                    const int32_t* __restrict__ chunk_begin,
                                                    const double* __restrict__ tab, const double* __restrict__ csw,
-                                                   int64_t N, int R1, int64_t M, double* __restrict__ gpart) {
-  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+                                                   int64_t N, int R1, int64_t M, double* __restrict__ gpart,
+    const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  __shared__ double s_g[kWaves][2 * D][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
   const int64_t jj = j < N ? j : N - 1;
   const int q = blockIdx.y;
-  const int r0 = chunk_begin[q], r1 = chunk_begin[q + 1];
+  const int r0 = chunk_begin[kWaves * q + wave], r1 = chunk_begin[kWaves * q + wave + 1];
   const cdd z = tab_entry(tab, N, R1, D - 1, 1, jj);
   double gh[D], gl[D];
 #pragma unroll
@@ -306,11 +341,22 @@ __global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs
     lazy_acc(gh[D - 1], gl[D - 1], qdh, qdl);
     renorm(gh[D - 1], gl[D - 1]);
   }
-  if (j < N) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    s_g[wave][2 * a][lane] = gh[a];
+    s_g[wave][2 * a + 1][lane] = gl[a];
+  }
+  __syncthreads();
+  if (wave == 0 && j < N) {  // ((w0 + w2) + (w1 + w3))
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      gpart[((int64_t)(q * 2 + 0) * D + a) * N + j] = gh[a];
-      gpart[((int64_t)(q * 2 + 1) * D + a) * N + j] = gl[a];
+      const dd x02 = dd_add(dd{s_g[0][2 * a][lane], s_g[0][2 * a + 1][lane]},
+                            dd{s_g[2][2 * a][lane], s_g[2][2 * a + 1][lane]});
+      const dd x13 = dd_add(dd{s_g[1][2 * a][lane], s_g[1][2 * a + 1][lane]},
+                            dd{s_g[3][2 * a][lane], s_g[3][2 * a + 1][lane]});
+      const dd g = dd_add(x02, x13);
+      gpart[((int64_t)(q * 2 + 0) * D + a) * N + j] = g.h;
+      gpart[((int64_t)(q * 2 + 1) * D + a) * N + j] = g.l;
     }
   }
 }
@@ -318,7 +364,9 @@ __global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs
 // sum the Q gradient partials (fixed order) and scale by 4 pi / L:
 // dPhi/dr_{j,a} = (4 pi / L) sum_k v_k n_{k,a} (S_k c_jk - C_k s_jk)
 __global__ void __launch_bounds__(kThreads) k_grad_combine(const double* __restrict__ gpart, int Q, int d, int64_t N,
-                                                           double L, double* __restrict__ grad) {
+                                                           double L, double* __restrict__ grad,
+    const int* __restrict__ active) {
+  if (active && *active == 0) return;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // a * N + j
   const int64_t DN = (int64_t)d * N;
   if (i >= DN) return;
@@ -469,73 +517,76 @@ __global__ void __launch_bounds__(kThreads) k_weights(const int32_t* __restrict_
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 // ---------------------------------------------------------------------------
-hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab, hipStream_t st) {
+hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab, hipStream_t st,
+                        const int* active) {
   const int64_t total = (int64_t)d * R1 * N;
   const int64_t blocks = (total + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_table, dim3((unsigned)blocks), dim3(kThreads), 0, st, pos, d, N, R1, tab);
+  hipLaunchKernelGGL(k_table, dim3((unsigned)blocks), dim3(kThreads), 0, st, pos, d, N, R1, tab, active);
   return hipGetLastError();
 }
 
 template <int D, int PT>
-static hipError_t launch_nk_t(const LaunchCfg& c, const Span* segs, int64_t nseg, const double* tab, double* part,
-                              hipStream_t st) {
+static hipError_t launch_nk_t(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units,
+                              int64_t nunits, const double* tab, double* part, hipStream_t st, const int* active) {
   const size_t lds = (size_t)PT * D * c.R1 * 4 * sizeof(double);
-  hipLaunchKernelGGL((k_nk<D, PT>), dim3((unsigned)c.segblocks, (unsigned)c.P), dim3(kThreads), lds, st, segs,
-                     nseg, tab, c.N, c.R1, c.chunk, part, c.M);
+  hipLaunchKernelGGL((k_nk<D, PT>), dim3((unsigned)nunits), dim3(kThreads), lds, st, segs, nseg, units, tab, c.N,
+                     c.R1, part, c.M, active);
   return hipGetLastError();
 }
 
 template <int D>
-static hipError_t launch_nk_d(const LaunchCfg& c, const Span* segs, int64_t nseg, const double* tab, double* part,
-                              hipStream_t st) {
+static hipError_t launch_nk_d(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units,
+                              int64_t nunits, const double* tab, double* part, hipStream_t st, const int* active) {
   switch (c.pt) {
-    case 16: return launch_nk_t<D, 16>(c, segs, nseg, tab, part, st);
-    case 4: return launch_nk_t<D, 4>(c, segs, nseg, tab, part, st);
-    default: return launch_nk_t<D, 1>(c, segs, nseg, tab, part, st);
+    case 16: return launch_nk_t<D, 16>(c, segs, nseg, units, nunits, tab, part, st, active);
+    case 4: return launch_nk_t<D, 4>(c, segs, nseg, units, nunits, tab, part, st, active);
+    default: return launch_nk_t<D, 1>(c, segs, nseg, units, nunits, tab, part, st, active);
   }
 }
 
-hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const double* tab, double* part,
-                     hipStream_t st) {
+hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units, int64_t nunits,
+                     const double* tab, double* part, hipStream_t st, const int* active) {
   switch (c.d) {
-    case 1: return launch_nk_d<1>(c, segs, nseg, tab, part, st);
-    case 2: return launch_nk_d<2>(c, segs, nseg, tab, part, st);
-    case 3: return launch_nk_d<3>(c, segs, nseg, tab, part, st);
-    default: return launch_nk_d<4>(c, segs, nseg, tab, part, st);
+    case 1: return launch_nk_d<1>(c, segs, nseg, units, nunits, tab, part, st, active);
+    case 2: return launch_nk_d<2>(c, segs, nseg, units, nunits, tab, part, st, active);
+    case 3: return launch_nk_d<3>(c, segs, nseg, units, nunits, tab, part, st, active);
+    default: return launch_nk_d<4>(c, segs, nseg, units, nunits, tab, part, st, active);
   }
 }
 
-hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* canon_of_lex, const double* v,
-                             double* nk_out, double* csw, double* blk, double* phi, double* smax, double* kmax,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_nk_combine, dim3((unsigned)c.combine_blocks), dim3(kThreads), 0, st, part, c.P, c.M, c.N,
-                     canon_of_lex, v, nk_out, csw, blk);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(kThreads), 0, st, blk, c.combine_blocks, phi, smax, kmax);
+hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* rows_of,
+                             const int32_t* canon_of_lex, const double* v, double* nk_out, double* csw, double* blk,
+                             double* phi, double* smax, double* kmax, hipStream_t st, const int* active) {
+  hipLaunchKernelGGL(k_nk_combine, dim3((unsigned)c.combine_blocks), dim3(kThreads), 0, st, part, rows_of, c.M, c.N,
+                     canon_of_lex, v, nk_out, csw, blk, active);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kThreads), 0, st, blk, c.combine_blocks, phi, smax, kmax, active);
   return hipGetLastError();
 }
 
 template <int D>
 static hipError_t launch_grad_d(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
-                                const double* csw, double* gpart, hipStream_t st) {
-  const int64_t blocks = (c.N + kThreads - 1) / kThreads;
+                                const double* csw, double* gpart, hipStream_t st, const int* active) {
+  const int64_t blocks = (c.N + 63) / 64;
   hipLaunchKernelGGL((k_grad<D>), dim3((unsigned)blocks, (unsigned)c.Q), dim3(kThreads), 0, st, runs, chunk_begin,
-                     tab, csw, c.N, c.R1, c.M, gpart);
+                     tab, csw, c.N, c.R1, c.M, gpart, active);
   return hipGetLastError();
 }
 
 hipError_t launch_grad(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
-                       const double* csw, double* gpart, double L, double* grad, hipStream_t st) {
-  hipError_t e;
+                       const double* csw, double* gpart, hipStream_t st, const int* active) {
   switch (c.d) {
-    case 1: e = launch_grad_d<1>(c, runs, chunk_begin, tab, csw, gpart, st); break;
-    case 2: e = launch_grad_d<2>(c, runs, chunk_begin, tab, csw, gpart, st); break;
-    case 3: e = launch_grad_d<3>(c, runs, chunk_begin, tab, csw, gpart, st); break;
-    default: e = launch_grad_d<4>(c, runs, chunk_begin, tab, csw, gpart, st); break;
+    case 1: return launch_grad_d<1>(c, runs, chunk_begin, tab, csw, gpart, st, active);
+    case 2: return launch_grad_d<2>(c, runs, chunk_begin, tab, csw, gpart, st, active);
+    case 3: return launch_grad_d<3>(c, runs, chunk_begin, tab, csw, gpart, st, active);
+    default: return launch_grad_d<4>(c, runs, chunk_begin, tab, csw, gpart, st, active);
   }
-  if (e != hipSuccess) return e;
+}
+
+hipError_t launch_grad_combine(const LaunchCfg& c, const double* gpart, double L, double* grad, hipStream_t st,
+                               const int* active) {
   const int64_t DN = (int64_t)c.d * c.N;
   hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((DN + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, gpart,
-                     c.Q, c.d, c.N, L, grad);
+                     c.Q, c.d, c.N, L, grad, active);
   return hipGetLastError();
 }
 

@@ -1,27 +1,31 @@
 // ss_lbfgs.hip -- device-resident L-BFGS quench of the stealthy energy.
 //
 // The paper quenches with FIRE ("Simulations" section) until Phi reaches the
-// smallest value the precision allows; this library minimises with the
-// limited-memory BFGS two-loop recursion (Nocedal & Wright, Numerical
-// Optimization, 2nd ed., Alg. 7.4) with an Armijo backtracking line search.
-// Every vector (positions, gradients, the (s, y) history) lives in device memory
-// as double-double [2][d N] planes; dot products are double-double with a fixed
-// reduction order.  The host only reads a few scalars per iteration to take the
-// line-search and stopping decisions.
+// smallest value the precision allows; this library minimises with L-BFGS and
+// an Armijo backtracking line search.  Everything lives on the device: the
+// positions, gradients and the (s, y) history as double-double [2][d N] planes,
+// and the minimiser's control state (iteration, line-search step, history
+// products, stopping tests) in a small struct in device memory.  One "tick" is a
+// fixed sequence of launches that advances the state machine by one trial
+// evaluation; the host enqueues ticks a few ahead and polls a status word copied
+// to pinned memory, so no blocking synchronisation sits inside the loop.
 //
-// Rules (shared with the CPU oracle's minimiser, which implements the same
-// rules independently):
-//  * stop "converged" when S_max <= s_floor;
-//  * direction p = -H g with H0 = (s.y / y.y) I of the newest pair; when the
-//    history is empty or g.p >= 0, reset the history and take the
-//    steepest-descent step p = -g * step_cap * N^(-1/d) / max|g|;
+// Rules (the CPU oracle's minimiser implements the same rules independently):
+//  * converged when S_max <= s_floor;
+//  * direction p = -H g, H the L-BFGS matrix of the kept pairs with
+//    H0 = (s.y / y.y) I of the newest pair, evaluated with the compact
+//    representation of Byrd, Nocedal & Schnabel (Math. Prog. 63, 1994,
+//    Thm 2.2), algebraically identical to the two-loop recursion of Nocedal &
+//    Wright (Alg. 7.4) that the oracle uses; when the history is empty or
+//    g.p >= 0, the history is cleared and p = -g step_cap N^(-1/d) / max|g|;
 //  * Armijo backtracking from alpha = 1 by halving, accept when
-//    Phi(x + alpha p) <= Phi(x) + c1 alpha g.p; after max_halvings halvings
-//    record a failure, reset the history and keep x;
-//  * keep the pair (s, y) = (x_new - x, g_new - g) only when s.y > 0;
-//  * stop "stalled" when min Phi over the last W iterations exceeds
-//    stall_ratio * min Phi over the W before, or after max_ls_fail
-//    consecutive failures; stop at max_iter.
+//    Phi(x + alpha p) <= Phi(x) + c1 alpha g.p; after max_halvings halvings a
+//    failure is recorded, the history cleared and x kept;
+//  * a pair (s, y) = (x_new - x, g_new - g) is kept only when s.y > 0, the
+//    oldest being dropped beyond `history` pairs;
+//  * stalled when min Phi over the last W iterations exceeds stall_ratio x min
+//    Phi over the W before, or after max_ls_fail consecutive failures; stops
+//    after max_iter iterations.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -38,135 +42,314 @@ namespace ss {
 int prepare(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg);
 int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg& c, const double* v_dev,
                      const double* pos, double* phi, double* smax, double* grad, double* nk, char* ws,
-                     hipStream_t st, double* kmax);
+                     hipStream_t st, double* kmax, const int* active);
 
 constexpr int kMaxHistory = 16;
-constexpr int kDotBlocks = 240;
+constexpr int kMaxWindow = 256;
+constexpr int kDotBlocks = 120;
+constexpr int kMaxDots = 2 + 2 * kMaxHistory;  // 34
+constexpr int kMaxComb = 1 + 2 * kMaxHistory;  // 33
+
+// control state of one quench (device memory)
+struct MinState {
+  int32_t running;    // 1 while the quench continues; every kernel of a tick reads it
+  int32_t status;     // 0 converged, 1 stalled, 2 iteration cap, 3 non-finite (valid once running == 0)
+  int32_t phase;      // 0: a new direction is needed; 1: a trial step is pending
+  int32_t new_dir;    // 1 when this tick computed a new direction
+  int32_t accepted;   // 1 when this tick accepted its trial
+  int32_t halvings, ls_fail, k, spare;
+  int32_t slot[kMaxHistory];  // history slots, oldest first
+  int32_t ncoef;
+  int32_t coef_vec[kMaxComb];  // 0: g, 1 + s: S[s], kMaxHistory + 2 + s: Y[s]
+  int64_t iter, evals;
+  double alpha;
+  double f[2], smax[2], ft[2], smaxt[2], gp[2];
+  double coef[kMaxComb][2];
+  double SY[kMaxHistory][kMaxHistory][2];  // s_i . y_j for i <= j (upper triangle R)
+  double YY[kMaxHistory][kMaxHistory][2];
+  double dir_dots[kMaxDots][2];    // s_i.g (k), y_i.g (k), g.g, max|g|
+  double trial_dots[kMaxDots][2];  // s.y, y.y, s_i.y (k), y.y_i (k) of the fresh pair
+  double fhist[2 * kMaxWindow][2];
+};
+
+struct MinParams {
+  int32_t m, W, max_halvings, max_ls_fail;
+  int64_t max_iter;
+  double s_floor, stall_ratio, c1, step;  // step = step_cap * N^(-1/d)
+};
+
+// the vectors of one quench
+struct VecSet {
+  double* x;  // positions (the caller's buffer)
+  double* g;
+  double* xt;
+  double* gt;
+  double* p;
+  double* S[kMaxHistory + 1];
+  double* Y[kMaxHistory + 1];
+};
+
+__device__ __forceinline__ dd ld(const double* a) { return dd{a[0], a[1]}; }
+__device__ __forceinline__ void st(double* a, dd v) {
+  a[0] = v.h;
+  a[1] = v.l;
+}
+__device__ __forceinline__ dd shfl_xor_dd(dd v, int m) {
+  return dd{__shfl_xor(v.h, m, 64), __shfl_xor(v.l, m, 64)};
+}
+__device__ __forceinline__ dd shfl_dd(dd v, int src) { return dd{__shfl(v.h, src, 64), __shfl(v.l, src, 64)}; }
+
+__device__ __forceinline__ const double* vec_of(const VecSet& V, int code) {
+  if (code == 0) return V.g;
+  if (code <= kMaxHistory + 1) return V.S[code - 1];
+  return V.Y[code - kMaxHistory - 2];
+}
+
+__device__ __forceinline__ dd vload(const double* p, int64_t nv, int64_t i) { return dd{p[i], p[nv + i]}; }
 
 // ---------------------------------------------------------------------------
-// vector kernels on dd planes [2][nv]
+// fixed-order multi-dot products.  Block (x, q) reduces element range x of
+// product q: strided sequential sums per lane, xor butterfly per wave, waves in
+// order; the last block to finish sums each product's range partials in order.
+// mode 0: direction products (operands from the history); mode 1: the trial
+// pair s = xt - x, y = gt - g (computed on the fly; blocks of product 0 also
+// write it to S[spare], Y[spare]) against the history.
 // ---------------------------------------------------------------------------
-
-// Fixed-order dot product a.b: each block reduces a fixed contiguous range
-// (thread-strided sequential sums, then a tree); the last block to finish
-// combines the block partials in block order and applies `op`:
-//   0: out = dot    1: out = s0 * dot    2: out = s1 - s0 * dot
-//   3: out = s0 / dot    4: out = dot, out2 = 1 / dot
-// For op 5 the kernel computes max_i |a_i| instead and out = c / max.
-__global__ void __launch_bounds__(kThreads) k_dot(const double* __restrict__ a, const double* __restrict__ b,
-                                                  int64_t nv, double* __restrict__ partial,
-                                                  unsigned int* __restrict__ counter, int op,
-                                                  const double* __restrict__ s0, const double* __restrict__ s1,
-                                                  double c, double* __restrict__ out, double* __restrict__ out2) {
-  __shared__ double sh[kThreads], sl[kThreads];
+__global__ void __launch_bounds__(kThreads) k_dots(VecSet V, MinState* S_, int mode, int64_t nv,
+                                                   double* __restrict__ partial, unsigned int* __restrict__ counter) {
+  MinState& S = *S_;
+  if (!S.running) return;
+  if (mode == 0 && S.phase != 0) return;
+  __shared__ double s_h[kThreads / 64], s_l[kThreads / 64];
   __shared__ bool is_last;
-  const int tid = threadIdx.x;
-  const int64_t per = (nv + gridDim.x - 1) / gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = blockIdx.y;
+  const int G = gridDim.x;
+  const int k = S.k;
+  const int n = 2 * k + 2;
+  const int64_t per = (nv + G - 1) / G;
   const int64_t i0 = (int64_t)blockIdx.x * per;
   const int64_t i1 = i0 + per < nv ? i0 + per : nv;
+  const int spare = S.spare;
+  if (mode == 1 && q == 0) {
+    double* so = V.S[spare];
+    double* yo = V.Y[spare];
+    for (int64_t i = i0 + tid; i < i1; i += kThreads) {
+      const dd a = dd_sub(vload(V.xt, nv, i), vload(V.x, nv, i));
+      const dd b = dd_sub(vload(V.gt, nv, i), vload(V.g, nv, i));
+      so[i] = a.h;
+      so[nv + i] = a.l;
+      yo[i] = b.h;
+      yo[nv + i] = b.l;
+    }
+  }
+  const bool isdot = !(mode == 0 && q == 2 * k + 1);
   dd acc{0.0, 0.0};
-  for (int64_t i = i0 + tid; i < i1; i += kThreads) {
-    const dd x{a[i], a[nv + i]};
-    if (op == 5) {
-      const dd ax = x.h < 0.0 ? dd_neg(x) : x;
-      if (dd_less(acc, ax)) acc = ax;
+  if (q < n) {
+    // operand codes: fa / fb = 1 fresh s, 2 fresh y, 0 the pointer pa / pb
+    const double* pa = nullptr;
+    const double* pb = nullptr;
+    int fa = 0, fb = 0;
+    if (mode == 0) {
+      pb = V.g;
+      if (q < k) pa = V.S[S.slot[q]];
+      else if (q < 2 * k) pa = V.Y[S.slot[q - k]];
+      else pa = V.g;  // g.g, and max|g| for q = 2k + 1
     } else {
-      acc = dd_add(acc, dd_mul(x, dd{b[i], b[nv + i]}));
+      if (q == 0) {
+        fa = 1;
+        fb = 2;
+      } else if (q == 1) {
+        fa = 2;
+        fb = 2;
+      } else if (q < 2 + k) {
+        pa = V.S[S.slot[q - 2]];
+        fb = 2;
+      } else {
+        fa = 2;
+        pb = V.Y[S.slot[q - 2 - k]];
+      }
+    }
+    for (int64_t i = i0 + tid; i < i1; i += kThreads) {
+      dd x;
+      if (fa == 1) x = dd_sub(vload(V.xt, nv, i), vload(V.x, nv, i));
+      else if (fa == 2) x = dd_sub(vload(V.gt, nv, i), vload(V.g, nv, i));
+      else x = vload(pa, nv, i);
+      if (!isdot) {
+        const dd ax = x.h < 0.0 ? dd_neg(x) : x;
+        if (dd_less(acc, ax)) acc = ax;
+        continue;
+      }
+      const dd y = fb == 2 ? dd_sub(vload(V.gt, nv, i), vload(V.g, nv, i)) : vload(pb, nv, i);
+      acc = dd_add(acc, dd_mul(x, y));
+    }
+    for (int mm = 32; mm > 0; mm >>= 1) {
+      const dd o = shfl_xor_dd(acc, mm);
+      acc = isdot ? dd_add(acc, o) : (dd_less(acc, o) ? o : acc);
+    }
+    if (lane == 0) {
+      s_h[wave] = acc.h;
+      s_l[wave] = acc.l;
     }
   }
-  sh[tid] = acc.h;
-  sl[tid] = acc.l;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      const dd x{sh[tid], sl[tid]}, y{sh[tid + w], sl[tid + w]};
-      const dd r = op == 5 ? (dd_less(x, y) ? y : x) : dd_add(x, y);
-      sh[tid] = r.h;
-      sl[tid] = r.l;
-    }
-    __syncthreads();
-  }
   if (tid == 0) {
-    partial[2 * blockIdx.x] = sh[0];
-    partial[2 * blockIdx.x + 1] = sl[0];
+    if (q < n) {
+      dd r{s_h[0], s_l[0]};
+      for (int w = 1; w < kThreads / 64; ++w) {
+        const dd o{s_h[w], s_l[w]};
+        r = isdot ? dd_add(r, o) : (dd_less(r, o) ? o : r);
+      }
+      partial[((int64_t)q * G + blockIdx.x) * 2] = r.h;
+      partial[((int64_t)q * G + blockIdx.x) * 2 + 1] = r.l;
+    }
     __threadfence();
-    const unsigned int prev = atomicAdd(counter, 1u);
-    is_last = (prev == gridDim.x - 1);
+    is_last = atomicAdd(counter, 1u) == gridDim.x * gridDim.y - 1;
   }
   __syncthreads();
   if (!is_last) return;
   __threadfence();
-  if (tid == 0) {
+  if (tid < n) {
+    const bool dotq = !(mode == 0 && tid == 2 * k + 1);
     dd r{0.0, 0.0};
-    for (unsigned int q = 0; q < gridDim.x; ++q) {
-      const dd y{partial[2 * q], partial[2 * q + 1]};
-      r = op == 5 ? (dd_less(r, y) ? y : r) : dd_add(r, y);
+    for (int blk = 0; blk < G; ++blk) {
+      const dd o{partial[((int64_t)tid * G + blk) * 2], partial[((int64_t)tid * G + blk) * 2 + 1]};
+      r = dotq ? dd_add(r, o) : (dd_less(r, o) ? o : r);
     }
-    dd res = r;
-    if (op == 1) res = dd_mul(dd{s0[0], s0[1]}, r);
-    else if (op == 2) res = dd_sub(dd{s1[0], s1[1]}, dd_mul(dd{s0[0], s0[1]}, r));
-    else if (op == 3) res = dd_div(dd{s0[0], s0[1]}, r);
-    else if (op == 5) res = r.h > 0.0 ? dd_div(dd{c, 0.0}, r) : dd{0.0, 0.0};
-    out[0] = res.h;
-    out[1] = res.l;
-    if (op == 4 && out2) {
-      const dd inv = r.h > 0.0 ? dd_div(dd{1.0, 0.0}, r) : dd{0.0, 0.0};
-      out2[0] = inv.h;
-      out2[1] = inv.l;
-    }
-    *counter = 0u;  // ready for the next reduction
+    st(mode == 0 ? S.dir_dots[tid] : S.trial_dots[tid], r);
   }
+  if (tid == 0) *counter = 0u;
 }
 
-// y <- y + sgn * coef * x, coef a device dd scalar
-__global__ void __launch_bounds__(kThreads) k_axpy(double* __restrict__ y, const double* __restrict__ x, int64_t nv,
-                                                   const double* __restrict__ coef, double sgn) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= nv) return;
-  const dd c{sgn * coef[0], sgn * coef[1]};
-  const dd r = dd_add(dd{y[i], y[nv + i]}, dd_mul(c, dd{x[i], x[nv + i]}));
-  y[i] = r.h;
-  y[nv + i] = r.l;
+// ---------------------------------------------------------------------------
+// one wave: the direction.  Compact form with H0 = gamma I:
+//   H g = gamma g + S top - gamma Y z,  R z = u,  R^T top = D z + gamma (Y^T Y z - w)
+// with u = S^T g, w = Y^T g, R the upper triangle of S^T Y and D its diagonal.
+// Lane i holds row i; the triangular solves run column by column.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_direction(MinState* S_, MinParams P) {
+  MinState& S = *S_;
+  if (!S.running || S.phase != 0) {
+    if (threadIdx.x == 0) S.new_dir = 0;
+    return;
+  }
+  const int i = threadIdx.x;
+  const int k = S.k;
+  const dd gg = ld(S.dir_dots[2 * k]);
+  const dd gmax = ld(S.dir_dots[2 * k + 1]);
+  bool use_sd = (k == 0);
+  dd gp{0.0, 0.0};
+  if (!use_sd) {
+    const dd gamma = dd_div(ld(S.SY[k - 1][k - 1]), ld(S.YY[k - 1][k - 1]));
+    // back substitution R z = u, column by column (rows i < j updated with z_j)
+    dd acc = i < k ? ld(S.dir_dots[i]) : dd{0.0, 0.0};
+    dd zi{0.0, 0.0};
+    for (int j = k - 1; j >= 0; --j) {
+      if (i == j) zi = dd_div(acc, ld(S.SY[j][j]));
+      const dd zj = shfl_dd(zi, j);
+      if (i < j) acc = dd_sub(acc, dd_mul(ld(S.SY[i][j]), zj));
+    }
+    // rhs_i = D_i z_i + gamma (sum_j YY_ij z_j - w_i)
+    dd rhs{0.0, 0.0};
+    dd t{0.0, 0.0};
+    for (int j = 0; j < k; ++j) {
+      const dd zj = shfl_dd(zi, j);
+      if (i < k) t = dd_add(t, dd_mul(ld(S.YY[i][j]), zj));
+    }
+    if (i < k) {
+      t = dd_sub(t, ld(S.dir_dots[k + i]));
+      rhs = dd_add(dd_mul(ld(S.SY[i][i]), zi), dd_mul(gamma, t));
+    }
+    // forward substitution R^T top = rhs, column by column (rows i > j updated)
+    dd topi{0.0, 0.0};
+    acc = rhs;
+    for (int j = 0; j < k; ++j) {
+      if (i == j) topi = dd_div(acc, ld(S.SY[j][j]));
+      const dd tj = shfl_dd(topi, j);
+      if (i > j && i < k) acc = dd_sub(acc, dd_mul(ld(S.SY[j][i]), tj));
+    }
+    // coefficients; g.p = sum coef * (vector . g) in a fixed order
+    const dd cs = dd_neg(topi);       // on S[slot_i]
+    const dd cy = dd_mul(gamma, zi);  // on Y[slot_i]
+    if (i < k) {
+      st(S.coef[1 + i], cs);
+      st(S.coef[1 + k + i], cy);
+      S.coef_vec[1 + i] = 1 + S.slot[i];
+      S.coef_vec[1 + k + i] = kMaxHistory + 2 + S.slot[i];
+    }
+    gp = dd_mul(dd_neg(gamma), gg);
+    for (int j = 0; j < k; ++j) {
+      const dd a = shfl_dd(cs, j), b = shfl_dd(cy, j);
+      gp = dd_add(gp, dd_mul(a, ld(S.dir_dots[j])));
+      gp = dd_add(gp, dd_mul(b, ld(S.dir_dots[k + j])));
+    }
+    if (i == 0) {
+      st(S.coef[0], dd_neg(gamma));
+      S.coef_vec[0] = 0;
+    }
+    if (!(gp.h < 0.0 || (gp.h == 0.0 && gp.l < 0.0))) use_sd = true;
+  }
+  __syncthreads();
+  if (i != 0) return;
+  if (use_sd) {
+    S.k = 0;
+    if (gmax.h == 0.0) {  // stationary point
+      S.status = 0;
+      S.running = 0;
+      S.new_dir = 0;
+      return;
+    }
+    const dd scale = dd_div(dd{P.step, 0.0}, gmax);
+    st(S.coef[0], dd_neg(scale));
+    S.coef_vec[0] = 0;
+    S.ncoef = 1;
+    gp = dd_neg(dd_mul(scale, gg));
+  } else {
+    S.ncoef = 1 + 2 * k;
+  }
+  st(S.gp, gp);
+  S.alpha = 1.0;
+  S.halvings = 0;
+  S.phase = 1;
+  S.new_dir = 1;
+  // the candidate pair goes to a slot no kept pair uses
+  int spare = 0;
+  for (;; ++spare) {
+    bool used = false;
+    for (int h = 0; h < S.k; ++h) used |= (S.slot[h] == spare);
+    if (!used) break;
+  }
+  S.spare = spare;
 }
 
-// y <- sgn * coef * x (coef a device dd scalar); x may alias y
-__global__ void __launch_bounds__(kThreads) k_scale(double* y, const double* x, int64_t nv,
-                                                    const double* __restrict__ coef, double sgn) {
+// p <- sum_c coef_c v_c (accurate dd sums in c order)
+__global__ void __launch_bounds__(kThreads) k_lincomb(VecSet V, const MinState* S_, int64_t nv) {
+  const MinState& S = *S_;
+  if (!S.running || !S.new_dir) return;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= nv) return;
-  const dd c{sgn * coef[0], sgn * coef[1]};
-  const dd r = dd_mul(c, dd{x[i], x[nv + i]});
-  y[i] = r.h;
-  y[nv + i] = r.l;
+  dd acc{0.0, 0.0};
+  for (int c = 0; c < S.ncoef; ++c) acc = dd_add(acc, dd_mul(ld(S.coef[c]), vload(vec_of(V, S.coef_vec[c]), nv, i)));
+  V.p[i] = acc.h;
+  V.p[nv + i] = acc.l;
 }
 
-// z <- x + alpha * p (alpha an exact power of two)
-__global__ void __launch_bounds__(kThreads) k_step(double* __restrict__ z, const double* __restrict__ x,
-                                                   const double* __restrict__ p, int64_t nv, double alpha) {
+// xt <- x + alpha p (alpha a power of two)
+__global__ void __launch_bounds__(kThreads) k_step(VecSet V, const MinState* S_, int64_t nv) {
+  const MinState& S = *S_;
+  if (!S.running) return;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= nv) return;
-  const dd r = dd_add(dd{x[i], x[nv + i]}, dd{alpha * p[i], alpha * p[nv + i]});
-  z[i] = r.h;
-  z[nv + i] = r.l;
-}
-
-// s <- xt - x, y <- gt - g
-__global__ void __launch_bounds__(kThreads) k_pair(double* __restrict__ s, double* __restrict__ y,
-                                                   const double* __restrict__ xt, const double* __restrict__ x,
-                                                   const double* __restrict__ gt, const double* __restrict__ g,
-                                                   int64_t nv) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= nv) return;
-  const dd a = dd_sub(dd{xt[i], xt[nv + i]}, dd{x[i], x[nv + i]});
-  const dd b = dd_sub(dd{gt[i], gt[nv + i]}, dd{g[i], g[nv + i]});
-  s[i] = a.h;
-  s[nv + i] = a.l;
-  y[i] = b.h;
-  y[nv + i] = b.l;
+  const double a = S.alpha;
+  const dd r = dd_add(vload(V.x, nv, i), dd{a * V.p[i], a * V.p[nv + i]});
+  V.xt[i] = r.h;
+  V.xt[nv + i] = r.l;
 }
 
 // gradient with respect to the fractional coordinates: g <- L * dPhi/dr
-__global__ void __launch_bounds__(kThreads) k_times_L(double* __restrict__ g, int64_t nv, double L) {
+__global__ void __launch_bounds__(kThreads) k_times_L(double* __restrict__ g, int64_t nv, double L,
+                                                      const int* __restrict__ active) {
+  if (active && *active == 0) return;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= nv) return;
   const dd r = dd_mul_d(dd{g[i], g[nv + i]}, L);
@@ -174,97 +357,208 @@ __global__ void __launch_bounds__(kThreads) k_times_L(double* __restrict__ g, in
   g[nv + i] = r.l;
 }
 
+// start-of-iteration tests (the top of the loop in the rules above), one thread
+__device__ void top_of_iteration(MinState& S, const MinParams& P) {
+  const int64_t it = S.iter;
+  const int W = P.W;
+  st(S.fhist[it % (2 * W)], ld(S.f));
+  if (!(S.smax[0] > P.s_floor || (S.smax[0] == P.s_floor && S.smax[1] > 0.0))) {
+    S.status = 0;
+    S.running = 0;
+    return;
+  }
+  if (it >= P.max_iter) {
+    S.status = 2;
+    S.running = 0;
+    return;
+  }
+  if (it >= 2 * (int64_t)W) {
+    dd recent = ld(S.fhist[it % (2 * W)]), older = ld(S.fhist[(it - W) % (2 * W)]);
+    for (int64_t q = it - W + 1; q <= it; ++q) {
+      const dd v = ld(S.fhist[q % (2 * W)]);
+      if (dd_less(v, recent)) recent = v;
+    }
+    for (int64_t q = it - 2 * W + 1; q <= it - W; ++q) {
+      const dd v = ld(S.fhist[q % (2 * W)]);
+      if (dd_less(v, older)) older = v;
+    }
+    if (dd_less(dd_mul_d(older, P.stall_ratio), recent)) {
+      S.status = 1;
+      S.running = 0;
+    }
+  }
+}
+
+// after the starting evaluation (f, smax set): finite check and the tests
+__global__ void k_init(MinState* S_, MinParams P) {
+  MinState& S = *S_;
+  S.iter = 0;
+  S.evals = 1;
+  S.k = 0;
+  S.phase = 0;
+  S.new_dir = 0;
+  S.accepted = 0;
+  S.ls_fail = 0;
+  S.halvings = 0;
+  S.spare = 0;
+  S.alpha = 1.0;
+  S.running = 1;
+  S.status = 2;
+  if (!isfinite(S.f[0])) {
+    S.status = 3;
+    S.running = 0;
+    return;
+  }
+  top_of_iteration(S, P);
+}
+
+// one wave: the Armijo test and its consequences
+__global__ void __launch_bounds__(64) k_decide(MinState* S_, MinParams P) {
+  MinState& S = *S_;
+  const int i = threadIdx.x;
+  __shared__ int s_push, s_drop;
+  if (!S.running) {
+    if (i == 0) S.accepted = 0;
+    return;
+  }
+  if (i == 0) {
+    S.evals += 1;
+    const dd f = ld(S.f), ft = ld(S.ft);
+    const dd bound = dd_add(f, dd_mul(dd_mul_d(dd{S.alpha, 0.0}, P.c1), ld(S.gp)));
+    s_push = 0;
+    s_drop = 0;
+    if (!dd_less(bound, ft)) {  // accepted
+      S.accepted = 1;
+      S.ls_fail = 0;
+      if (S.trial_dots[0][0] > 0.0) {
+        s_push = 1;
+        s_drop = (S.k == P.m) ? 1 : 0;
+      }
+    } else {
+      S.accepted = 0;
+      S.alpha *= 0.5;
+      S.halvings += 1;
+    }
+  }
+  __syncthreads();
+  const int k = S.k;
+  if (s_push) {
+    // drop the oldest pair when full, then append the fresh pair as the newest
+    // column of the upper triangle of S^T Y and row/column of Y^T Y
+    const int first = s_drop;
+    const int kept = k - first;
+    dd colsy{0.0, 0.0}, colyy{0.0, 0.0};
+    if (i < k) {
+      colsy = ld(S.trial_dots[2 + i]);
+      colyy = ld(S.trial_dots[2 + k + i]);
+    }
+    if (first) {
+      dd rowsy[kMaxHistory], rowyy[kMaxHistory];
+      if (i < k)
+        for (int j = 0; j < k; ++j) {
+          rowsy[j] = ld(S.SY[i][j]);
+          rowyy[j] = ld(S.YY[i][j]);
+        }
+      __syncthreads();
+      if (i >= 1 && i < k)
+        for (int j = 1; j < k; ++j) {
+          st(S.SY[i - 1][j - 1], rowsy[j]);
+          st(S.YY[i - 1][j - 1], rowyy[j]);
+        }
+    }
+    __syncthreads();
+    if (i >= first && i < k) {
+      st(S.SY[i - first][kept], colsy);
+      st(S.YY[i - first][kept], colyy);
+      st(S.YY[kept][i - first], colyy);
+    }
+    __syncthreads();
+    if (i == 0) {
+      st(S.SY[kept][kept], ld(S.trial_dots[0]));
+      st(S.YY[kept][kept], ld(S.trial_dots[1]));
+      for (int h = first; h < k; ++h) S.slot[h - first] = S.slot[h];
+      S.slot[kept] = S.spare;
+      S.k = kept + 1;
+    }
+  }
+  __syncthreads();
+  if (i != 0) return;
+  if (S.accepted) {
+    S.f[0] = S.ft[0];
+    S.f[1] = S.ft[1];
+    S.smax[0] = S.smaxt[0];
+    S.smax[1] = S.smaxt[1];
+    S.iter += 1;
+    S.phase = 0;
+    if (!isfinite(S.f[0])) {
+      S.status = 3;
+      S.running = 0;
+      return;
+    }
+    top_of_iteration(S, P);
+  } else if (S.halvings > P.max_halvings) {  // line-search failure: keep x, clear the history
+    S.ls_fail += 1;
+    S.k = 0;
+    S.iter += 1;
+    S.phase = 0;
+    if (S.ls_fail >= P.max_ls_fail) {
+      st(S.fhist[S.iter % (2 * P.W)], ld(S.f));
+      S.status = 1;
+      S.running = 0;
+      return;
+    }
+    top_of_iteration(S, P);
+  }
+}
+
+// x <- xt, g <- gt after an accepted trial
+__global__ void __launch_bounds__(kThreads) k_accept(VecSet V, const MinState* S_, int64_t nv) {
+  if (!S_->accepted) return;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= nv) return;
+  V.x[i] = V.xt[i];
+  V.x[nv + i] = V.xt[nv + i];
+  V.g[i] = V.gt[i];
+  V.g[nv + i] = V.gt[nv + i];
+}
+
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
-// ---------------------------------------------------------------------------
-// host double-double helpers (the line-search and stall decisions)
-// ---------------------------------------------------------------------------
 namespace {
-
-struct hdd {
-  double h, l;
-};
-
-inline hdd h_two_sum(double a, double b) {
-  const double s = a + b;
-  const double bb = s - a;
-  return hdd{s, (a - (s - bb)) + (b - bb)};
-}
-inline hdd h_fast(double a, double b) {
-  const double s = a + b;
-  return hdd{s, b - (s - a)};
-}
-inline hdd h_add(hdd a, hdd b) {
-  hdd s = h_two_sum(a.h, b.h);
-  hdd t = h_two_sum(a.l, b.l);
-  s.l += t.h;
-  s = h_fast(s.h, s.l);
-  s.l += t.l;
-  return h_fast(s.h, s.l);
-}
-inline hdd h_mul_d(hdd a, double b) {
-  const double p = a.h * b;
-  double e = fma(a.h, b, -p);
-  e = fma(a.l, b, e);
-  return h_fast(p, e);
-}
-inline hdd h_mul(hdd a, hdd b) {
-  const double p = a.h * b.h;
-  double e = fma(a.h, b.h, -p);
-  double t = a.l * b.l;
-  t = fma(a.h, b.l, t);
-  t = fma(a.l, b.h, t);
-  e += t;
-  return h_fast(p, e);
-}
-inline bool h_less(hdd a, hdd b) { return a.h < b.h || (a.h == b.h && a.l < b.l); }
-
-struct Vecs {
-  int64_t nv;
-  double *g, *xt, *gt, *p, *q;
-  double* S[kMaxHistory + 1];
-  double* Y[kMaxHistory + 1];
-  double* scal;  // device scalars (dd pairs), see Slot*
-  double* partial;
-  unsigned int* counter;
-  size_t bytes;
-};
-
-// device scalar slots (each a dd = 2 doubles)
-enum {
-  kPhi = 0, kSmax, kPhiT, kSmaxT, kSy, kGp, kGamma, kYY, kTmp, kCoef, kKmax,
-  kRho = 16, kAlpha = kRho + kMaxHistory + 1, kSyH = kAlpha + kMaxHistory + 1,
-  kNumScal = kSyH + kMaxHistory + 1
-};
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t lbfgs_bytes(int64_t nv) {
   const size_t vec = al256(sizeof(double) * 2 * (size_t)nv);
-  return vec * (5 + 2 * (kMaxHistory + 1)) + al256(sizeof(double) * 2 * kNumScal) +
-         al256(sizeof(double) * 2 * kDotBlocks) + 256;
+  return vec * (4 + 2 * (kMaxHistory + 1)) + al256(sizeof(MinState)) +
+         al256(sizeof(double) * 2 * kMaxDots * kDotBlocks) + 256;
 }
 
-void carve(char* base, int64_t nv, Vecs* v) {
+struct Layout {
+  VecSet V;
+  MinState* state;
+  double* partial;
+  unsigned int* counter;
+};
+
+void carve(char* base, int64_t nv, double* x, Layout* L) {
   const size_t vec = al256(sizeof(double) * 2 * (size_t)nv);
   size_t off = 0;
-  v->nv = nv;
   auto take = [&](size_t n) {
     char* p = base + off;
     off += n;
     return p;
   };
-  v->g = (double*)take(vec);
-  v->xt = (double*)take(vec);
-  v->gt = (double*)take(vec);
-  v->p = (double*)take(vec);
-  v->q = (double*)take(vec);
-  for (int i = 0; i <= kMaxHistory; ++i) v->S[i] = (double*)take(vec);
-  for (int i = 0; i <= kMaxHistory; ++i) v->Y[i] = (double*)take(vec);
-  v->scal = (double*)take(al256(sizeof(double) * 2 * kNumScal));
-  v->partial = (double*)take(al256(sizeof(double) * 2 * kDotBlocks));
-  v->counter = (unsigned int*)take(256);
-  v->bytes = off;
+  L->V.x = x;
+  L->V.g = (double*)take(vec);
+  L->V.xt = (double*)take(vec);
+  L->V.gt = (double*)take(vec);
+  L->V.p = (double*)take(vec);
+  for (int i = 0; i <= kMaxHistory; ++i) L->V.S[i] = (double*)take(vec);
+  for (int i = 0; i <= kMaxHistory; ++i) L->V.Y[i] = (double*)take(vec);
+  L->state = (MinState*)take(al256(sizeof(MinState)));
+  L->partial = (double*)take(al256(sizeof(double) * 2 * kMaxDots * kDotBlocks));
+  L->counter = (unsigned int*)take(256);
 }
 
 }  // namespace
@@ -274,46 +568,6 @@ size_t minimize_extra_bytes(int64_t nv) { return lbfgs_bytes(nv); }
 }  // namespace ss
 
 using namespace ss;
-
-namespace {
-
-struct Runner {
-  ss_ctx* ctx;
-  hipStream_t st;
-  Vecs v;
-  int blocks_nv;
-  int dot_blocks;
-  int err = SS_OK;
-
-  bool ok(hipError_t e, const char* what) {
-    if (e != hipSuccess && err == SS_OK) {
-      ctx->last_error = std::string(what) + ": " + hipGetErrorString(e);
-      err = e == hipErrorOutOfMemory ? SS_ENOMEM : SS_EHIP;
-    }
-    return err == SS_OK;
-  }
-  double* sc(int slot) { return v.scal + 2 * slot; }
-  void dot(const double* a, const double* b, int op, int out, const double* s0 = nullptr,
-           const double* s1 = nullptr, double c = 0.0, double* out2 = nullptr) {
-    hipLaunchKernelGGL(k_dot, dim3(dot_blocks), dim3(kThreads), 0, st, a, b, v.nv, v.partial, v.counter, op, s0, s1,
-                       c, sc(out), out2);
-    ok(hipGetLastError(), "k_dot");
-  }
-  void axpy(double* y, const double* x, const double* coef, double sgn) {
-    hipLaunchKernelGGL(k_axpy, dim3(blocks_nv), dim3(kThreads), 0, st, y, x, v.nv, coef, sgn);
-    ok(hipGetLastError(), "k_axpy");
-  }
-  void scale(double* y, const double* x, const double* coef, double sgn) {
-    hipLaunchKernelGGL(k_scale, dim3(blocks_nv), dim3(kThreads), 0, st, y, x, v.nv, coef, sgn);
-    ok(hipGetLastError(), "k_scale");
-  }
-  bool fetch(int slot, int count, double* host) {
-    if (!ok(hipMemcpyAsync(host, sc(slot), sizeof(double) * 2 * count, hipMemcpyDeviceToHost, st), "fetch")) return false;
-    return ok(hipStreamSynchronize(st), "sync");
-  }
-};
-
-}  // namespace
 
 extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
                            double* pos_dev, const ss_min_opts* op, ss_min_result* out, void* ws, size_t ws_bytes,
@@ -332,7 +586,8 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
     return SS_EINVAL;
   }
   if (op->history < 1 || op->history > kMaxHistory || op->max_iter < 0 || op->stall_window < 1 ||
-      op->max_halvings < 0 || op->max_ls_fail < 1 || !(op->step_cap > 0.0) || !(op->c1 > 0.0 && op->c1 < 1.0)) {
+      op->stall_window > kMaxWindow || op->max_halvings < 0 || op->max_ls_fail < 1 || !(op->step_cap > 0.0) ||
+      !(op->c1 > 0.0 && op->c1 < 1.0) || !(op->stall_ratio > 0.0)) {
     ctx->last_error = "invalid minimiser options";
     return SS_EINVAL;
   }
@@ -342,187 +597,103 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
     return SS_EINVAL;
   }
   const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = (hipStream_t)stream;
   char* ews = (char*)ws;
-  Runner R{ctx, (hipStream_t)stream, {}, (int)((nv + kThreads - 1) / kThreads), 1};
-  carve(ews + c.total, nv, &R.v);
-  R.dot_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (nv + 1023) / 1024));
-  const int m = op->history;
+  Layout Lay;
+  carve(ews + c.total, nv, pos_dev, &Lay);
+  VecSet& V = Lay.V;
+  MinState* S = Lay.state;
+  MinParams P;
+  P.m = op->history;
+  P.W = op->stall_window;
+  P.max_halvings = op->max_halvings;
+  P.max_ls_fail = op->max_ls_fail;
+  P.max_iter = op->max_iter;
+  P.s_floor = op->s_floor;
+  P.stall_ratio = op->stall_ratio;
+  P.c1 = op->c1;
+  P.step = op->step_cap * pow((double)prob->N, -1.0 / (double)prob->d);
+  const int blocks_nv = (int)((nv + kThreads - 1) / kThreads);
+  const int dot_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (nv + 1023) / 1024));
   const double L = prob->L;
-  Vecs& V = R.v;
-  hipStream_t st = R.st;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, V.counter);
-  R.ok(hipGetLastError(), "k_zero_u32");
-
-  auto eval = [&](const double* x, int phi_slot, double* g) -> bool {
-    int e = energy_grad_impl(ctx, prob, pl, c, v_dev, x, R.sc(phi_slot), R.sc(phi_slot + 1), g, nullptr, ews, st,
-                             nullptr);
+  int err = SS_OK;
+  auto ok = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && err == SS_OK) {
+      ctx->last_error = std::string(what) + ": " + hipGetErrorString(e);
+      err = e == hipErrorOutOfMemory ? SS_ENOMEM : SS_EHIP;
+    }
+    return err == SS_OK;
+  };
+  const int* running = &S->running;
+  auto eval = [&](const double* x, double* phi, double* smax, double* g, const int* active) -> bool {
+    int e = energy_grad_impl(ctx, prob, pl, c, v_dev, x, phi, smax, g, nullptr, ews, st, nullptr, active);
     if (e) {
-      if (R.err == SS_OK) R.err = e;
+      if (err == SS_OK) err = e;
       return false;
     }
-    if (g && L != 1.0) {
-      hipLaunchKernelGGL(k_times_L, dim3(R.blocks_nv), dim3(kThreads), 0, st, g, nv, L);
-      R.ok(hipGetLastError(), "k_times_L");
+    if (L != 1.0) {
+      hipLaunchKernelGGL(k_times_L, dim3(blocks_nv), dim3(kThreads), 0, st, g, nv, L, active);
+      ok(hipGetLastError(), "k_times_L");
     }
-    return R.err == SS_OK;
+    return err == SS_OK;
   };
 
-  double hbuf[8];
-  int64_t evals = 0, gevals = 0;
-  if (!eval(pos_dev, kPhi, V.g) || !R.fetch(kPhi, 2, hbuf)) return R.err;
-  ++evals;
-  ++gevals;
-  hdd f{hbuf[0], hbuf[1]}, smax{hbuf[2], hbuf[3]};
-  if (!std::isfinite(f.h)) {
-    out->status = 3;
-    out->iters = 0;
-    out->evals = evals;
-    out->grad_evals = gevals;
-    out->phi[0] = f.h;
-    out->phi[1] = f.l;
-    out->smax[0] = smax.h;
-    out->smax[1] = smax.l;
-    out->seconds = 0.0;
-    ctx->last_error = "non-finite energy at the starting positions";
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, Lay.counter);
+  ok(hipGetLastError(), "k_zero_u32");
+  if (!eval(pos_dev, S->f, S->smax, V.g, nullptr)) return err;
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(1), 0, st, S, P);
+  ok(hipGetLastError(), "k_init");
+
+  // ticks, enqueued kDepth ahead; the status word of each tick is copied to
+  // pinned memory and read once that tick's event has completed
+  constexpr int kDepth = 3;
+  int32_t* flags = nullptr;
+  hipEvent_t ev[kDepth] = {};
+  if (!ok(hipHostMalloc((void**)&flags, sizeof(int32_t) * kDepth, hipHostMallocDefault), "hipHostMalloc")) return err;
+  for (int q = 0; q < kDepth && err == SS_OK; ++q) ok(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "event");
+  int64_t tick = 0;
+  while (err == SS_OK) {
+    hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 0, nv, Lay.partial,
+                       Lay.counter);
+    hipLaunchKernelGGL(k_direction, dim3(1), dim3(64), 0, st, S, P);
+    hipLaunchKernelGGL(k_lincomb, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
+    hipLaunchKernelGGL(k_step, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
+    if (!ok(hipGetLastError(), "direction kernels")) break;
+    if (!eval(V.xt, S->ft, S->smaxt, V.gt, running)) break;
+    hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 1, nv, Lay.partial,
+                       Lay.counter);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, S, P);
+    hipLaunchKernelGGL(k_accept, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
+    if (!ok(hipGetLastError(), "decision kernels")) break;
+    const int q = (int)(tick % kDepth);
+    if (!ok(hipMemcpyAsync(flags + q, running, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag copy")) break;
+    if (!ok(hipEventRecord(ev[q], st), "event record")) break;
+    ++tick;
+    if (tick >= kDepth) {
+      const int w = (int)(tick % kDepth);  // the oldest tick in flight
+      if (!ok(hipEventSynchronize(ev[w]), "event sync")) break;
+      if (flags[w] == 0) break;
+    }
+  }
+  ok(hipStreamSynchronize(st), "final sync");
+  MinState hs;
+  if (err == SS_OK) ok(hipMemcpy(&hs, S, sizeof(MinState), hipMemcpyDeviceToHost), "state copy");
+  for (int q = 0; q < kDepth; ++q)
+    if (ev[q]) hipEventDestroy(ev[q]);
+  hipHostFree(flags);
+  if (err != SS_OK) return err;
+  out->status = hs.status;
+  out->iters = hs.iter;
+  out->evals = hs.evals;
+  out->grad_evals = hs.evals;
+  out->phi[0] = hs.f[0];
+  out->phi[1] = hs.f[1];
+  out->smax[0] = hs.smax[0];
+  out->smax[1] = hs.smax[1];
+  out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (hs.status == 3) {
+    ctx->last_error = "non-finite energy";
     return SS_ENUMERIC;
   }
-  const double nmean = pow((double)prob->N, -1.0 / (double)prob->d);
-  std::vector<int> ring;  // slots, oldest first
-  std::vector<int> free_slots;
-  for (int i = 0; i <= m; ++i) free_slots.push_back(m - i);
-  std::vector<hdd> fhist;
-  const int64_t W = op->stall_window;
-  int ls_fail = 0;
-  int status = 2;
-  int64_t it = 0;
-  for (;;) {
-    fhist.push_back(f);
-    if (!(smax.h > op->s_floor || (smax.h == op->s_floor && smax.l > 0.0))) {
-      status = 0;
-      break;
-    }
-    if (it >= op->max_iter) {
-      status = 2;
-      break;
-    }
-    if (it >= 2 * W) {
-      hdd recent = fhist[it], older = fhist[it - W];
-      for (int64_t i = it - W + 1; i <= it; ++i)
-        if (h_less(fhist[i], recent)) recent = fhist[i];
-      for (int64_t i = it - 2 * W + 1; i <= it - W; ++i)
-        if (h_less(fhist[i], older)) older = fhist[i];
-      if (h_less(h_mul_d(older, op->stall_ratio), recent)) {
-        status = 1;
-        break;
-      }
-    }
-    bool use_sd = ring.empty();
-    hdd gp{0.0, 0.0};
-    if (!use_sd) {
-      // two-loop recursion on q = g
-      R.ok(hipMemcpyAsync(V.q, V.g, sizeof(double) * 2 * nv, hipMemcpyDeviceToDevice, st), "copy q");
-      for (int h = (int)ring.size() - 1; h >= 0; --h) {
-        const int s = ring[h];
-        R.dot(V.S[s], V.q, 1, kAlpha + s, R.sc(kRho + s));       // alpha_s = rho_s s.q
-        R.axpy(V.q, V.Y[s], R.sc(kAlpha + s), -1.0);             // q -= alpha_s y_s
-      }
-      const int nw = ring.back();
-      R.dot(V.Y[nw], V.Y[nw], 3, kGamma, R.sc(kSyH + nw));       // gamma = s.y / y.y
-      R.scale(V.q, V.q, R.sc(kGamma), 1.0);
-      for (size_t h = 0; h < ring.size(); ++h) {
-        const int s = ring[h];
-        R.dot(V.Y[s], V.q, 2, kCoef, R.sc(kRho + s), R.sc(kAlpha + s));  // alpha_s - rho_s y.r
-        R.axpy(V.q, V.S[s], R.sc(kCoef), 1.0);
-      }
-      R.dot(V.g, V.q, 0, kGp);                                   // g.q = -g.p
-      if (!R.fetch(kGp, 1, hbuf)) return R.err;
-      gp = hdd{-hbuf[0], -hbuf[1]};
-      if (!(gp.h < 0.0 || (gp.h == 0.0 && gp.l < 0.0))) use_sd = true;
-      else std::swap(V.p, V.q);  // p = -q is applied in the step (sign folded below)
-    }
-    double dir_sign = -1.0;  // p_dev holds -p for the two-loop direction
-    if (use_sd) {
-      for (int s : ring) free_slots.push_back(s);
-      ring.clear();
-      R.dot(V.g, V.g, 5, kTmp, nullptr, nullptr, op->step_cap * nmean);  // scale = step / max|g|
-      R.scale(V.p, V.g, R.sc(kTmp), 1.0);                                  // p_dev = scale g = -p
-      R.dot(V.g, V.p, 0, kGp);
-      if (!R.fetch(kGp, 1, hbuf)) return R.err;
-      gp = hdd{-hbuf[0], -hbuf[1]};
-      if (gp.h == 0.0) {
-        status = 0;
-        break;
-      }
-    }
-    // Armijo backtracking; each trial also computes the gradient and the
-    // candidate pair into the spare history slot
-    const int spare = free_slots.back();
-    double alpha = 1.0;
-    bool accepted = false;
-    hdd ft{0, 0}, smt{0, 0}, sy{0, 0};
-    for (int hcount = 0; hcount <= op->max_halvings; ++hcount) {
-      hipLaunchKernelGGL(k_step, dim3(R.blocks_nv), dim3(kThreads), 0, st, V.xt, pos_dev, V.p, nv, dir_sign * alpha);
-      R.ok(hipGetLastError(), "k_step");
-      if (!eval(V.xt, kPhiT, V.gt)) return R.err;
-      ++evals;
-      ++gevals;
-      hipLaunchKernelGGL(k_pair, dim3(R.blocks_nv), dim3(kThreads), 0, st, V.S[spare], V.Y[spare], V.xt, pos_dev,
-                         V.gt, V.g, nv);
-      R.ok(hipGetLastError(), "k_pair");
-      R.dot(V.S[spare], V.Y[spare], 4, kSyH + spare, nullptr, nullptr, 0.0, R.sc(kRho + spare));
-      R.ok(hipMemcpyAsync(R.sc(kSy), R.sc(kSyH + spare), 2 * sizeof(double), hipMemcpyDeviceToDevice, st),
-           "copy sy");
-      if (!R.fetch(kPhiT, 3, hbuf)) return R.err;  // PhiT, SmaxT, Sy in one read
-      ft = hdd{hbuf[0], hbuf[1]};
-      smt = hdd{hbuf[2], hbuf[3]};
-      sy = hdd{hbuf[4], hbuf[5]};
-      const hdd bound = h_add(f, h_mul(h_mul_d(hdd{alpha, 0.0}, op->c1), gp));
-      if (!h_less(bound, ft)) {
-        accepted = true;
-        break;
-      }
-      alpha *= 0.5;
-    }
-    ++it;
-    if (!accepted) {
-      ++ls_fail;
-      for (int s : ring) free_slots.push_back(s);
-      ring.clear();
-      if (ls_fail >= op->max_ls_fail) {
-        fhist.push_back(f);
-        status = 1;
-        break;
-      }
-      continue;
-    }
-    ls_fail = 0;
-    if (sy.h > 0.0) {
-      free_slots.pop_back();
-      ring.push_back(spare);
-      if ((int)ring.size() > m) {
-        free_slots.push_back(ring.front());
-        ring.erase(ring.begin());
-      }
-    }
-    R.ok(hipMemcpyAsync(pos_dev, V.xt, sizeof(double) * 2 * nv, hipMemcpyDeviceToDevice, st), "copy x");
-    std::swap(V.g, V.gt);
-    R.ok(hipMemcpyAsync(R.sc(kPhi), R.sc(kPhiT), 4 * sizeof(double), hipMemcpyDeviceToDevice, st), "copy phi");
-    f = ft;
-    smax = smt;
-    if (!std::isfinite(f.h)) {
-      status = 3;
-      break;
-    }
-  }
-  if (!R.ok(hipStreamSynchronize(st), "final sync")) return R.err;
-  out->status = status;
-  out->iters = it;
-  out->evals = evals;
-  out->grad_evals = gevals;
-  out->phi[0] = f.h;
-  out->phi[1] = f.l;
-  out->smax[0] = smax.h;
-  out->smax[1] = smax.l;
-  out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return status == 3 ? SS_ENUMERIC : SS_OK;
+  return SS_OK;
 }

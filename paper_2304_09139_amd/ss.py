@@ -62,6 +62,8 @@ SIGNATURES = {
     "ss_workspace_size": (ctypes.c_int, [_V, ctypes.POINTER(Problem), ctypes.c_int, _SZP]),
     "ss_energy_grad": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V, _V, _V, _V, _V, _V,
                                       ctypes.c_size_t, _V]),
+    "ss_profile_enable": (ctypes.c_int, [_V, ctypes.c_int]),
+    "ss_profile_read": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int, _I64P, ctypes.POINTER(ctypes.c_double)]),
     "ss_minimize": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V, ctypes.POINTER(MinOpts),
                                    ctypes.POINTER(MinResult), _V, ctypes.c_size_t, _V]),
 }
@@ -160,6 +162,19 @@ class Context:
 
     def _chk(self, rc, what):
         return _check(rc, self._h, what)
+
+    KERNELS = {"nk": 0, "grad": 1, "table": 2}
+
+    def profile(self, enable: bool = True) -> None:
+        self._chk(lib().ss_profile_enable(self._h, 1 if enable else 0), "ss_profile_enable")
+
+    def profile_read(self, kernel: str, reset: bool = True) -> tuple[int, float]:
+        """(launches, total milliseconds) of one kernel since the last reset."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        self._chk(lib().ss_profile_read(self._h, self.KERNELS[kernel], 1 if reset else 0, ctypes.byref(n),
+                                        ctypes.byref(ms)), "ss_profile_read")
+        return n.value, ms.value
 
     def wavevectors(self, d: int, R2: int) -> torch.Tensor:
         M = ctypes.c_int64()
