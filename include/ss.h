@@ -132,13 +132,14 @@ int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, co
                    const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
                    void* ws, size_t ws_bytes, void* stream);
 
-/* Per-kernel timing for measurement (off by default).  When enabled, every
- * launch of the n~(k) pass (kernel 0), the gradient pass (kernel 1) and the
- * phase-table kernel (kernel 2) is bracketed by hipEvents recorded on the
- * caller's stream.  ss_profile_read synchronises on the recorded events and
- * returns the number of launches and their summed duration in milliseconds;
- * reset != 0 then forgets them. */
-int ss_profile_enable(ss_ctx* ctx, int enable);
+/* Per-kernel timing for measurement (off by default).  `mask` selects the
+ * kernels: bit 0 the n~(k) pass (kernel 0), bit 1 the gradient pass (kernel 1),
+ * bit 2 the phase-table kernel (kernel 2); 0 turns timing off.  Every launch of
+ * a selected kernel is bracketed by hipEvents recorded on the caller's stream.
+ * ss_profile_read synchronises on the recorded events and returns the number
+ * of launches and their summed duration in milliseconds; reset != 0 then
+ * forgets them.  SS_EINVAL for a mask outside 0..7. */
+int ss_profile_enable(ss_ctx* ctx, int mask);
 int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, double* total_ms);
 
 /* Options of the L-BFGS quench (ss_minimize).  The paper quenches with FIRE

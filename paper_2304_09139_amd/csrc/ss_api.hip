@@ -28,6 +28,8 @@ hipError_t launch_grad_combine(const LaunchCfg& c, const double* gpart, double L
 hipError_t launch_weights(const int32_t* n, int64_t M, int d, int64_t R2, int vkind, double* v, hipStream_t st);
 hipError_t enumerate(int d, int64_t R2, int R, hipStream_t st, Plan* pl);
 size_t minimize_extra_bytes(int64_t nv);
+int grad_blocks_per_cu(int d);
+int nk_blocks_per_cu(int d, int pt, int R1);
 }  // namespace ss
 
 using namespace ss;
@@ -176,19 +178,50 @@ int chunk_bounds(ss_ctx* ctx, Plan* pl, int Q, int32_t** out) {
   return SS_OK;
 }
 
+// Grids are sized in whole "rounds" of resident blocks (blocks per CU x CUs) so
+// that the last round is not left mostly idle.
+int num_cus(ss_ctx* ctx) {
+  static int cached = 0;
+  if (!cached) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || n <= 0) n = 256;
+    cached = n;
+  }
+  return cached;
+}
+
+// Work split into `per` blocks per step, at most max_steps steps: the step count
+// whose block total fills its last round of `capacity` resident blocks best,
+// trying 1..rounds rounds (stops at the first that is at least 90% full).
+int64_t rounds_fit(int64_t capacity, int64_t per, int64_t max_steps, int rounds) {
+  int64_t best = 1;
+  double best_eff = -1.0;
+  for (int r = 1; r <= rounds; ++r) {
+    const int64_t steps = std::max<int64_t>(1, std::min<int64_t>(max_steps, (capacity * r) / per));
+    const int64_t blocks = steps * per;
+    const int64_t full = (blocks + capacity - 1) / capacity;
+    const double eff = (double)blocks / (double)(full * capacity);
+    if (eff > best_eff + 0.05 || (r == 1 && eff >= 0.9)) {
+      best_eff = eff;
+      best = steps;
+      if (eff >= 0.9) break;
+    }
+  }
+  return best;
+}
+
 // n(k) pass schedule for N particles: piece block b gets P_b particle ranges
 // whose work (longest piece + base cost) x (particles) is about equal across all
-// units, about kTargetBlocks units in total; wavevectors of block b then have P_b
-// partial rows.  Depends only on (d, R2, N).
-constexpr int64_t kTargetBlocks = 2048;     // n(k) pass units (blocks of 4 waves)
-constexpr int64_t kTargetGradBlocks = 2048;  // gradient pass blocks (4 waves each)
-
+// units, about two rounds of resident blocks in total; wavevectors of block b then
+// have P_b partial rows.  Depends only on (d, R2, N) and the device.
 int nk_schedule(ss_ctx* ctx, Plan* pl, int64_t N, int pt, Plan::NkSched** out) {
   auto it = pl->nk_sched.find(N);
   if (it != pl->nk_sched.end()) {
     *out = &it->second;
     return SS_OK;
   }
+  // two rounds of resident blocks
+  const int64_t kTargetBlocks = 2 * (int64_t)num_cus(ctx) * nk_blocks_per_cu(pl->d, pt, pl->R + 1);
   const size_t nb = pl->block_maxlen.size();
   double wsum = 0.0;
   for (int L : pl->block_maxlen) wsum += L + 1.5;
@@ -250,10 +283,10 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c) {
   // gradient pass: blocks of 64 particles x Q chunks, each wave of a block on one
   // of kWaves sub-chunks of equal pair count
   const int64_t pblocks = (c->N + 63) / 64;
-  int64_t Q = (kTargetGradBlocks + pblocks - 1) / pblocks;
-  Q = std::max<int64_t>(1, std::min<int64_t>(Q, std::min<int64_t>(std::max<int64_t>(1, pl->nruns / kWaves), 1024)));
-  c->Q = (int)Q;
-  c->combine_blocks = (c->M + 63) / 64;
+  const int64_t capacity = (int64_t)num_cus(ctx) * grad_blocks_per_cu(p->d);
+  const int64_t maxQ = std::min<int64_t>(std::max<int64_t>(1, pl->nruns / kWaves), 1024);
+  c->Q = (int)rounds_fit(capacity, pblocks, maxQ, 4);
+  c->combine_blocks = (c->M + kCombK - 1) / kCombK;
   size_t off = 0;
   c->off_tab = off;
   off += align256((size_t)p->d * c->R1 * 4 * c->N * sizeof(double));
@@ -314,7 +347,7 @@ hipEvent_t prof_event(ss_ctx* ctx) {
 // records an event pair around `launch` on `st` when profiling is enabled
 template <class F>
 hipError_t timed(ss_ctx* ctx, int which, hipStream_t st, F launch) {
-  if (!ctx->prof.enabled) return launch();
+  if (!(ctx->prof.mask & (1 << which))) return launch();
   hipEvent_t a = prof_event(ctx), b = prof_event(ctx);
   if (a) hipEventRecord(a, st);
   hipError_t e = launch();
@@ -337,7 +370,7 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
   SS_HIP(ctx, timed(ctx, 2, st, [&] { return launch_table(pos, p->d, p->N, c.R1, tab, st, active); }));
   Plan::NkSched* sc = &pl->nk_sched.at(p->N);
   SS_HIP(ctx, timed(ctx, 0, st, [&] { return launch_nk(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, st, active); }));
-  SS_HIP(ctx, launch_nk_combine(c, part, sc->rows_of, pl->canon_of_lex, v, nk, csw, blk, phi ? phi : scal,
+  SS_HIP(ctx, launch_nk_combine(c, part, sc->rows_of, pl->canon_of_lex, v, nk, csw, blk, phi,
                                 smax ? smax : scal + 2, kmax, st, active));
   if (grad) {
     int32_t* cb = nullptr;
@@ -487,10 +520,10 @@ int ss_workspace_size(ss_ctx* ctx, const ss_problem* prob, int op, size_t* bytes
   return SS_OK;
 }
 
-int ss_profile_enable(ss_ctx* ctx, int enable) {
-  if (!ctx) return SS_EINVAL;
+int ss_profile_enable(ss_ctx* ctx, int mask) {
+  if (!ctx || mask < 0 || mask > 7) return SS_EINVAL;
   std::lock_guard<std::mutex> g(ctx->mu);
-  ctx->prof.enabled = enable != 0;
+  ctx->prof.mask = mask;
   return SS_OK;
 }
 

@@ -70,13 +70,15 @@ constexpr int kSegLen = 8;        // wavevectors per lane in the n(k) pass
 constexpr int kThreads = 256;     // threads per block
 constexpr int kWaves = 4;         // waves per block
 constexpr int kNkPieces = 256;    // run pieces per n(k) block (one per lane)
+constexpr int kTabRun = 8;        // phase-table exponents per thread (one sin/cos pair each)
+constexpr int kCombK = 32;        // wavevectors per block of the partial combine
 
 }  // namespace ss
 
 namespace ss {
 // optional per-kernel timing: hipEvent pairs recorded on the launch stream
 struct ProfileLog {
-  bool enabled = false;
+  int mask = 0;  // bit k: time kernel k
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];  // 0 n(k) pass, 1 gradient pass, 2 phase table
   std::vector<hipEvent_t> pool;
 };

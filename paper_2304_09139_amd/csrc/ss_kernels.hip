@@ -28,6 +28,7 @@
 
 #include "ss_dd.h"
 #include "ss_internal.h"
+#include "ss_reduce.h"
 
 namespace ss {
 
@@ -39,21 +40,31 @@ __global__ void __launch_bounds__(kThreads) k_table(const double* __restrict__ p
                                                     double* __restrict__ tab,
     const int* __restrict__ active) {
   if (active && *active == 0) return;
+  // thread (a, group of kTabRun exponents m0 .. m0 + kTabRun - 1, particle j):
+  // z^m0 and z by the exact reduction and the dd sin/cos, then z^m = z^(m-1) z
   const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t total = (int64_t)d * R1 * N;
+  const int groups = (R1 + kTabRun - 1) / kTabRun;
+  const int64_t total = (int64_t)d * groups * N;
   if (idx >= total) return;
   const int64_t j = idx % N;
-  const int64_t am = idx / N;
-  const int m = (int)(am % R1);
-  const int a = (int)(am / R1);
+  const int64_t ag = idx / N;
+  const int m0 = (int)(ag % groups) * kTabRun;
+  const int a = (int)(ag / groups);
   const double uh = pos[(int64_t)a * N + j];
   const double ul = pos[(int64_t)(d + a) * N + j];
-  const cdd z = expi2pi(phase_of((double)m, uh, ul));
-  const int64_t base = am * 4 * N + j;
-  tab[base] = z.rh;
-  tab[base + N] = z.rl;
-  tab[base + 2 * N] = z.ih;
-  tab[base + 3 * N] = z.il;
+  cdd w = expi2pi(phase_of((double)m0, uh, ul));
+  const cdd z = expi2pi(phase_of(1.0, uh, ul));
+  for (int t = 0; t < kTabRun && m0 + t < R1; ++t) {
+    if (t > 0) w = cmul(w, z);
+    double rh, rl, ih, il;
+    fast_two_sum(w.rh, w.rl, rh, rl);
+    fast_two_sum(w.ih, w.il, ih, il);
+    const int64_t base = ((int64_t)(a * R1 + m0 + t) * 4) * N + j;
+    tab[base] = rh;
+    tab[base + N] = rl;
+    tab[base + 2 * N] = ih;
+    tab[base + 3 * N] = il;
+  }
 }
 
 // entry z_a^m of the particle table staged in LDS ([a][m][c] per particle),
@@ -150,16 +161,18 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restric
                                                          double* __restrict__ csw, double* __restrict__ blk,
     const int* __restrict__ active) {
   if (active && *active == 0) return;
-  // thread (q, g): wavevector i = block * 64 + q, partial group g sums p = g, g+4, ...
-  __shared__ double s_c[kWaves][4][64];
-  __shared__ double s_ph[64], s_pl[64], s_mh[64], s_ml[64];
-  __shared__ int64_t s_mk[64];
-  const int tid = threadIdx.x, q = tid & 63, g = tid >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + q;
+  // thread (q, g): wavevector i = block * kCombK + q; partial group g sums rows
+  // g, g + kCombG, ...; the groups are then added pairwise in a fixed tree
+  constexpr int kCombG = kThreads / kCombK;
+  __shared__ double s_c[kCombG][4][kCombK];
+  __shared__ double s_ph[kCombK], s_pl[kCombK], s_mh[kCombK], s_ml[kCombK];
+  __shared__ int64_t s_mk[kCombK];
+  const int tid = threadIdx.x, q = tid % kCombK, g = tid / kCombK;
+  const int64_t i = (int64_t)blockIdx.x * kCombK + q;
   dd C{0.0, 0.0}, S{0.0, 0.0};
   if (i < M) {
     const int64_t P = rows_of[i];
-    for (int64_t p = g; p < P; p += kWaves) {
+    for (int64_t p = g; p < P; p += kCombG) {
       const double* r = part + p * 4 * M;
       C = dd_add(C, dd{r[i], r[M + i]});
       S = dd_add(S, dd{r[2 * M + i], r[3 * M + i]});
@@ -170,13 +183,20 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restric
   s_c[g][2][q] = S.h;
   s_c[g][3][q] = S.l;
   __syncthreads();
-  if (g == 0) {  // ((g0 + g2) + (g1 + g3))
-    dd c02 = dd_add(dd{s_c[0][0][q], s_c[0][1][q]}, dd{s_c[2][0][q], s_c[2][1][q]});
-    dd c13 = dd_add(dd{s_c[1][0][q], s_c[1][1][q]}, dd{s_c[3][0][q], s_c[3][1][q]});
-    dd s02 = dd_add(dd{s_c[0][2][q], s_c[0][3][q]}, dd{s_c[2][2][q], s_c[2][3][q]});
-    dd s13 = dd_add(dd{s_c[1][2][q], s_c[1][3][q]}, dd{s_c[3][2][q], s_c[3][3][q]});
-    C = dd_add(c02, c13);
-    S = dd_add(s02, s13);
+  for (int w = kCombG / 2; w > 0; w >>= 1) {
+    if (g < w) {
+      const dd c = dd_add(dd{s_c[g][0][q], s_c[g][1][q]}, dd{s_c[g + w][0][q], s_c[g + w][1][q]});
+      const dd sn = dd_add(dd{s_c[g][2][q], s_c[g][3][q]}, dd{s_c[g + w][2][q], s_c[g + w][3][q]});
+      s_c[g][0][q] = c.h;
+      s_c[g][1][q] = c.l;
+      s_c[g][2][q] = sn.h;
+      s_c[g][3][q] = sn.l;
+    }
+    __syncthreads();
+  }
+  if (g == 0) {
+    C = dd{s_c[0][0][q], s_c[0][1][q]};
+    S = dd{s_c[0][2][q], s_c[0][3][q]};
     dd phi{0.0, 0.0}, sk{-1.0, 0.0};
     int64_t kc = INT64_MAX;
     if (i < M) {
@@ -205,7 +225,7 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restric
     s_mk[q] = kc;
   }
   __syncthreads();
-  for (int w = 32; w > 0; w >>= 1) {
+  for (int w = kCombK / 2; w > 0; w >>= 1) {
     if (tid < w) {
       const dd a = dd_add(dd{s_ph[tid], s_pl[tid]}, dd{s_ph[tid + w], s_pl[tid + w]});
       s_ph[tid] = a.h;
@@ -233,47 +253,17 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restric
 __global__ void __launch_bounds__(kThreads) k_final(const double* __restrict__ blk, int64_t nblk,
                                                     double* __restrict__ phi_out, double* __restrict__ smax_out,
                                                     double* __restrict__ kmax_out,
-    const int* __restrict__ active) {
+                                                    const int* __restrict__ active) {
   if (active && *active == 0) return;
-  __shared__ double s_ph[kThreads], s_pl[kThreads], s_mh[kThreads], s_ml[kThreads], s_mk[kThreads];
-  const int tid = threadIdx.x;
-  dd phi{0.0, 0.0}, sk{-1.0, 0.0};
-  double kk = 1e300;
-  for (int64_t b = tid; b < nblk; b += kThreads) {
-    const double* q = blk + b * 5;
-    phi = dd_add(phi, dd{q[0], q[1]});
-    const dd y{q[2], q[3]};
-    if (dd_less(sk, y) || (!dd_less(y, sk) && q[4] < kk)) {
-      sk = y;
-      kk = q[4];
-    }
-  }
-  s_ph[tid] = phi.h;
-  s_pl[tid] = phi.l;
-  s_mh[tid] = sk.h;
-  s_ml[tid] = sk.l;
-  s_mk[tid] = kk;
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      const dd a = dd_add(dd{s_ph[tid], s_pl[tid]}, dd{s_ph[tid + w], s_pl[tid + w]});
-      s_ph[tid] = a.h;
-      s_pl[tid] = a.l;
-      const dd x{s_mh[tid], s_ml[tid]}, y{s_mh[tid + w], s_ml[tid + w]};
-      if (dd_less(x, y) || (!dd_less(y, x) && s_mk[tid + w] < s_mk[tid])) {
-        s_mh[tid] = y.h;
-        s_ml[tid] = y.l;
-        s_mk[tid] = s_mk[tid + w];
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    phi_out[0] = s_ph[0];
-    phi_out[1] = s_pl[0];
-    smax_out[0] = s_mh[0];
-    smax_out[1] = s_ml[0];
-    if (kmax_out) kmax_out[0] = s_mk[0];
+  dd phi, sm;
+  double kk;
+  reduce_energy_partials(blk, nblk, &phi, &sm, &kk);
+  if (threadIdx.x == 0) {
+    phi_out[0] = phi.h;
+    phi_out[1] = phi.l;
+    smax_out[0] = sm.h;
+    smax_out[1] = sm.l;
+    if (kmax_out) kmax_out[0] = kk;
   }
 }
 
@@ -519,7 +509,7 @@ __global__ void __launch_bounds__(kThreads) k_weights(const int32_t* __restrict_
 // ---------------------------------------------------------------------------
 hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab, hipStream_t st,
                         const int* active) {
-  const int64_t total = (int64_t)d * R1 * N;
+  const int64_t total = (int64_t)d * ((R1 + kTabRun - 1) / kTabRun) * N;
   const int64_t blocks = (total + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_table, dim3((unsigned)blocks), dim3(kThreads), 0, st, pos, d, N, R1, tab, active);
   return hipGetLastError();
@@ -559,7 +549,7 @@ hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32
                              double* phi, double* smax, double* kmax, hipStream_t st, const int* active) {
   hipLaunchKernelGGL(k_nk_combine, dim3((unsigned)c.combine_blocks), dim3(kThreads), 0, st, part, rows_of, c.M, c.N,
                      canon_of_lex, v, nk_out, csw, blk, active);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(kThreads), 0, st, blk, c.combine_blocks, phi, smax, kmax, active);
+  if (phi) hipLaunchKernelGGL(k_final, dim3(1), dim3(kThreads), 0, st, blk, c.combine_blocks, phi, smax, kmax, active);
   return hipGetLastError();
 }
 
@@ -588,6 +578,45 @@ hipError_t launch_grad_combine(const LaunchCfg& c, const double* gpart, double L
   hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((DN + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, gpart,
                      c.Q, c.d, c.N, L, grad, active);
   return hipGetLastError();
+}
+
+// resident blocks per CU of the two pair kernels (for grid sizing in whole rounds)
+template <int D>
+static int grad_bpc_d() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_grad<D>, kThreads, 0) != hipSuccess) b = 1;
+  return b > 0 ? b : 1;
+}
+int grad_blocks_per_cu(int d) {
+  switch (d) {
+    case 1: return grad_bpc_d<1>();
+    case 2: return grad_bpc_d<2>();
+    case 3: return grad_bpc_d<3>();
+    default: return grad_bpc_d<4>();
+  }
+}
+template <int D, int PT>
+static int nk_bpc_t(size_t lds) {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_nk<D, PT>, kThreads, lds) != hipSuccess) b = 1;
+  return b > 0 ? b : 1;
+}
+template <int D>
+static int nk_bpc_d(int pt, int R1) {
+  const size_t lds = (size_t)pt * D * R1 * 4 * sizeof(double);
+  switch (pt) {
+    case 16: return nk_bpc_t<D, 16>(lds);
+    case 4: return nk_bpc_t<D, 4>(lds);
+    default: return nk_bpc_t<D, 1>(lds);
+  }
+}
+int nk_blocks_per_cu(int d, int pt, int R1) {
+  switch (d) {
+    case 1: return nk_bpc_d<1>(pt, R1);
+    case 2: return nk_bpc_d<2>(pt, R1);
+    case 3: return nk_bpc_d<3>(pt, R1);
+    default: return nk_bpc_d<4>(pt, R1);
+  }
 }
 
 hipError_t launch_weights(const int32_t* n, int64_t M, int d, int64_t R2, int vkind, double* v, hipStream_t st) {

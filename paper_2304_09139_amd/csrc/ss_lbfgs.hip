@@ -36,6 +36,7 @@
 #include "ss.h"
 #include "ss_dd.h"
 #include "ss_internal.h"
+#include "ss_reduce.h"
 
 namespace ss {
 
@@ -108,20 +109,352 @@ __device__ __forceinline__ const double* vec_of(const VecSet& V, int code) {
 __device__ __forceinline__ dd vload(const double* p, int64_t nv, int64_t i) { return dd{p[i], p[nv + i]}; }
 
 // ---------------------------------------------------------------------------
+// the direction (run by the last block of the direction products; rows live on
+// lanes i < k of wave 0).  Compact form with H0 = gamma I:
+//   H g = gamma g + S top - gamma Y z,  R z = u,  R^T top = D z + gamma (Y^T Y z - w)
+// with u = S^T g, w = Y^T g, R the upper triangle of S^T Y and D its diagonal.
+// The triangular solves run column by column, rows held in registers.
+// ---------------------------------------------------------------------------
+__device__ void direction_logic(MinState& S, const MinParams& P, int i) {
+  const int k = S.k;
+  const dd gg = ld(S.dir_dots[2 * k]);
+  const dd gmax = ld(S.dir_dots[2 * k + 1]);
+  bool use_sd = (k == 0);
+  dd gp{0.0, 0.0};
+  if (!use_sd) {
+    dd rowR[kMaxHistory], colR[kMaxHistory], rowYY[kMaxHistory];
+    const bool mine = i < k;
+#pragma unroll
+    for (int j = 0; j < kMaxHistory; ++j) {
+      rowR[j] = (mine && j < k) ? ld(S.SY[i][j]) : dd{0.0, 0.0};
+      colR[j] = (mine && j < k) ? ld(S.SY[j][i]) : dd{0.0, 0.0};
+      rowYY[j] = (mine && j < k) ? ld(S.YY[i][j]) : dd{0.0, 0.0};
+    }
+    const dd u = mine ? ld(S.dir_dots[i]) : dd{0.0, 0.0};
+    const dd w = mine ? ld(S.dir_dots[k + i]) : dd{0.0, 0.0};
+    const dd gamma = dd_div(ld(S.SY[k - 1][k - 1]), ld(S.YY[k - 1][k - 1]));
+    const dd diag = mine ? ld(S.SY[i][i]) : dd{1.0, 0.0};
+    const dd rdiag = dd_div(dd{1.0, 0.0}, diag);  // all lanes at once, off the serial chain
+    // back substitution R z = u (rows i < j updated with z_j)
+    dd acc = u, zi{0.0, 0.0};
+#pragma unroll
+    for (int j = kMaxHistory - 1; j >= 0; --j) {
+      if (j < k) {
+        if (i == j) zi = dd_mul(acc, rdiag);
+        const dd zj = shfl_dd(zi, j);
+        if (i < j) acc = dd_sub(acc, dd_mul(rowR[j], zj));
+      }
+    }
+    // rhs_i = D_i z_i + gamma (sum_j YY_ij z_j - w_i)
+    dd t{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < kMaxHistory; ++j) {
+      if (j < k) t = dd_add(t, dd_mul(rowYY[j], shfl_dd(zi, j)));
+    }
+    const dd rhs = dd_add(dd_mul(diag, zi), dd_mul(gamma, dd_sub(t, w)));
+    // forward substitution R^T top = rhs (rows i > j updated with top_j)
+    dd topi{0.0, 0.0};
+    acc = rhs;
+#pragma unroll
+    for (int j = 0; j < kMaxHistory; ++j) {
+      if (j < k) {
+        if (i == j) topi = dd_mul(acc, rdiag);
+        const dd tj = shfl_dd(topi, j);
+        if (i > j) acc = dd_sub(acc, dd_mul(colR[j], tj));
+      }
+    }
+    const dd cs = dd_neg(topi);       // on S[slot_i]
+    const dd cy = dd_mul(gamma, zi);  // on Y[slot_i]
+    if (mine) {
+      st(S.coef[1 + i], cs);
+      st(S.coef[1 + k + i], cy);
+      S.coef_vec[1 + i] = 1 + S.slot[i];
+      S.coef_vec[1 + k + i] = kMaxHistory + 2 + S.slot[i];
+    }
+    // g.p = sum coef * (vector . g) in a fixed order
+    gp = dd_mul(dd_neg(gamma), gg);
+#pragma unroll
+    for (int j = 0; j < kMaxHistory; ++j) {
+      if (j < k) {
+        gp = dd_add(gp, dd_mul(shfl_dd(cs, j), ld(S.dir_dots[j])));
+        gp = dd_add(gp, dd_mul(shfl_dd(cy, j), ld(S.dir_dots[k + j])));
+      }
+    }
+    if (i == 0) {
+      st(S.coef[0], dd_neg(gamma));
+      S.coef_vec[0] = 0;
+    }
+    if (!(gp.h < 0.0 || (gp.h == 0.0 && gp.l < 0.0))) use_sd = true;
+  }
+  if (i != 0) return;
+  if (use_sd) {
+    S.k = 0;
+    if (gmax.h == 0.0) {  // stationary point
+      S.status = 0;
+      S.running = 0;
+      S.new_dir = 0;
+      return;
+    }
+    const dd scale = dd_div(dd{P.step, 0.0}, gmax);
+    st(S.coef[0], dd_neg(scale));
+    S.coef_vec[0] = 0;
+    S.ncoef = 1;
+    gp = dd_neg(dd_mul(scale, gg));
+  } else {
+    S.ncoef = 1 + 2 * k;
+  }
+  st(S.gp, gp);
+  S.alpha = 1.0;
+  S.halvings = 0;
+  S.phase = 1;
+  S.new_dir = 1;
+  // the candidate pair goes to a slot no kept pair uses
+  int spare = 0;
+  for (;; ++spare) {
+    bool used = false;
+    for (int h = 0; h < S.k; ++h) used |= (S.slot[h] == spare);
+    if (!used) break;
+  }
+  S.spare = spare;
+}
+
+// p <- sum_c coef_c v_c (accurate dd sums in c order) when a new direction was
+// made this tick; then xt <- x + alpha p (alpha a power of two)
+__global__ void __launch_bounds__(kThreads) k_step(VecSet V, const MinState* S_, int64_t nv) {
+  const MinState& S = *S_;
+  if (!S.running) return;
+  __shared__ double s_ch[kMaxComb], s_cl[kMaxComb];
+  __shared__ const double* s_v[kMaxComb];
+  const int nd = S.new_dir;
+  const int nc = S.ncoef;
+  if (nd && threadIdx.x < nc) {
+    s_ch[threadIdx.x] = S.coef[threadIdx.x][0];
+    s_cl[threadIdx.x] = S.coef[threadIdx.x][1];
+    s_v[threadIdx.x] = vec_of(V, S.coef_vec[threadIdx.x]);
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= nv) return;
+  dd p;
+  if (nd) {
+    dd acc{0.0, 0.0};
+    for (int c = 0; c < nc; ++c) acc = dd_add(acc, dd_mul(dd{s_ch[c], s_cl[c]}, vload(s_v[c], nv, i)));
+    V.p[i] = acc.h;
+    V.p[nv + i] = acc.l;
+    p = acc;
+  } else {
+    p = vload(V.p, nv, i);
+  }
+  const double a = S.alpha;
+  const dd r = dd_add(vload(V.x, nv, i), dd{a * p.h, a * p.l});
+  V.xt[i] = r.h;
+  V.xt[nv + i] = r.l;
+}
+
+// gradient with respect to the fractional coordinates: g <- L * dPhi/dr
+__global__ void __launch_bounds__(kThreads) k_times_L(double* __restrict__ g, int64_t nv, double L,
+                                                      const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= nv) return;
+  const dd r = dd_mul_d(dd{g[i], g[nv + i]}, L);
+  g[i] = r.h;
+  g[nv + i] = r.l;
+}
+
+// start-of-iteration tests (the top of the loop in the rules above) for
+// iteration `it` with energy f and S_max smax; all 64 lanes of one wave call it
+// (they scan the stall window in parallel), lane 0 writes the state
+__device__ void top_of_iteration(MinState& S, const MinParams& P, int lane, int64_t it, dd f, dd smax) {
+  const int W = P.W;
+  int status = -1;
+  if (!(smax.h > P.s_floor || (smax.h == P.s_floor && smax.l > 0.0))) status = 0;
+  else if (it >= P.max_iter) status = 2;
+  else if (it >= 2 * (int64_t)W) {
+    dd recent = f, older{INFINITY, 0.0};
+    for (int64_t q = it - 2 * W + 1 + lane; q < it; q += 64) {
+      const dd v = ld(S.fhist[q % (2 * W)]);
+      if (q > it - W) {
+        if (dd_less(v, recent)) recent = v;
+      } else if (dd_less(v, older)) {
+        older = v;
+      }
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+      const dd r = shfl_xor_dd(recent, m), o = shfl_xor_dd(older, m);
+      if (dd_less(r, recent)) recent = r;
+      if (dd_less(o, older)) older = o;
+    }
+    if (dd_less(dd_mul_d(older, P.stall_ratio), recent)) status = 1;
+  }
+  if (lane == 0) {
+    st(S.fhist[it % (2 * W)], f);
+    if (status >= 0) {
+      S.status = status;
+      S.running = 0;
+    }
+  }
+}
+
+// after the starting evaluation (f, smax set): finite check and the tests
+__global__ void __launch_bounds__(64) k_init(MinState* S_, MinParams P) {
+  MinState& S = *S_;
+  const int lane = threadIdx.x;
+  if (lane == 0) {
+    S.iter = 0;
+    S.evals = 1;
+    S.k = 0;
+    S.phase = 0;
+    S.new_dir = 0;
+    S.accepted = 0;
+    S.ls_fail = 0;
+    S.halvings = 0;
+    S.spare = 0;
+    S.alpha = 1.0;
+    S.running = 1;
+    S.status = 2;
+  }
+  const dd f = ld(S.f), smax = ld(S.smax);  // written by the previous kernel
+  if (!isfinite(f.h)) {
+    if (lane == 0) {
+      S.status = 3;
+      S.running = 0;
+    }
+    return;
+  }
+  top_of_iteration(S, P, lane, 0, f, smax);
+}
+
+// the Armijo test and its consequences (run by the last block of the trial
+// products; all threads call it for the barriers, wave 0 does the work).  Lane 0
+// takes the decisions and hands them to the other lanes through LDS.
+__device__ void decide_logic(MinState& S, const MinParams& P, int i) {
+  __shared__ int s_push, s_drop, s_acc, s_top, s_run;
+  __shared__ long long s_it;
+  __shared__ double s_f[2], s_sm[2];
+  const int k = S.k;
+  if (i == 0) {
+    S.evals += 1;
+    const dd f = ld(S.f), ft = ld(S.ft);
+    const double alpha = S.alpha;
+    const dd bound = dd_add(f, dd_mul(dd_mul_d(dd{alpha, 0.0}, P.c1), ld(S.gp)));
+    int push = 0, drop = 0, acc = 0, top = 0, run = 1;
+    int64_t it = S.iter;
+    dd fn = f, smn = ld(S.smax);
+    if (!dd_less(bound, ft)) {  // accepted
+      acc = 1;
+      S.ls_fail = 0;
+      if (S.trial_dots[0][0] > 0.0) {
+        push = 1;
+        drop = (k == P.m) ? 1 : 0;
+      }
+      fn = ft;
+      smn = ld(S.smaxt);
+      st(S.f, fn);
+      st(S.smax, smn);
+      it += 1;
+      S.iter = it;
+      S.phase = 0;
+      top = 1;
+      if (!isfinite(fn.h)) {
+        S.status = 3;
+        S.running = 0;
+        run = 0;
+        top = 0;
+      }
+    } else {
+      S.alpha = alpha * 0.5;
+      const int h = S.halvings + 1;
+      S.halvings = h;
+      if (h > P.max_halvings) {  // line-search failure: keep x, clear the history
+        const int lf = S.ls_fail + 1;
+        S.ls_fail = lf;
+        S.k = 0;
+        it += 1;
+        S.iter = it;
+        S.phase = 0;
+        top = 1;
+        if (lf >= P.max_ls_fail) {
+          st(S.fhist[it % (2 * P.W)], fn);
+          S.status = 1;
+          S.running = 0;
+          run = 0;
+          top = 0;
+        }
+      }
+    }
+    S.accepted = acc;
+    s_push = push;
+    s_drop = drop;
+    s_acc = acc;
+    s_top = top;
+    s_run = run;
+    s_it = it;
+    s_f[0] = fn.h;
+    s_f[1] = fn.l;
+    s_sm[0] = smn.h;
+    s_sm[1] = smn.l;
+  }
+  __syncthreads();
+  if (s_push) {
+    // drop the oldest pair when full, then append the fresh pair as the newest
+    // column of the upper triangle of S^T Y and row/column of Y^T Y
+    const int first = s_drop;
+    const int kept = k - first;
+    const bool mine = i < k;
+    const dd colsy = mine ? ld(S.trial_dots[2 + i]) : dd{0.0, 0.0};
+    const dd colyy = mine ? ld(S.trial_dots[2 + k + i]) : dd{0.0, 0.0};
+    dd rowsy[kMaxHistory], rowyy[kMaxHistory];
+    if (first) {
+#pragma unroll
+      for (int j = 0; j < kMaxHistory; ++j) {
+        rowsy[j] = (mine && j < k) ? ld(S.SY[i][j]) : dd{0.0, 0.0};
+        rowyy[j] = (mine && j < k) ? ld(S.YY[i][j]) : dd{0.0, 0.0};
+      }
+    }
+    __syncthreads();
+    if (first && i >= 1 && mine) {
+#pragma unroll
+      for (int j = 1; j < kMaxHistory; ++j) {
+        if (j < k) {
+          st(S.SY[i - 1][j - 1], rowsy[j]);
+          st(S.YY[i - 1][j - 1], rowyy[j]);
+        }
+      }
+    }
+    __syncthreads();
+    if (i >= first && mine) {
+      st(S.SY[i - first][kept], colsy);
+      st(S.YY[i - first][kept], colyy);
+      st(S.YY[kept][i - first], colyy);
+    }
+    if (i == 0) {
+      st(S.SY[kept][kept], ld(S.trial_dots[0]));
+      st(S.YY[kept][kept], ld(S.trial_dots[1]));
+      for (int h = first; h < k; ++h) S.slot[h - first] = S.slot[h];
+      S.slot[kept] = S.spare;
+      S.k = kept + 1;
+    }
+  }
+  __syncthreads();
+  if (i >= 64) return;
+  if (s_top && s_run) top_of_iteration(S, P, i, s_it, dd{s_f[0], s_f[1]}, dd{s_sm[0], s_sm[1]});
+}
+
+// ---------------------------------------------------------------------------
 // fixed-order multi-dot products.  Block (x, q) reduces element range x of
-// product q: strided sequential sums per lane, xor butterfly per wave, waves in
-// order; the last block to finish sums each product's range partials in order.
+// product q (strided sequential sums per lane, xor butterfly per wave, waves in
+// order) into one partial; k_dots_final sums the partials in range order.
 // mode 0: direction products (operands from the history); mode 1: the trial
 // pair s = xt - x, y = gt - g (computed on the fly; blocks of product 0 also
 // write it to S[spare], Y[spare]) against the history.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_dots(VecSet V, MinState* S_, int mode, int64_t nv,
-                                                   double* __restrict__ partial, unsigned int* __restrict__ counter) {
+                                                   double* __restrict__ partial) {
   MinState& S = *S_;
   if (!S.running) return;
   if (mode == 0 && S.phase != 0) return;
   __shared__ double s_h[kThreads / 64], s_l[kThreads / 64];
-  __shared__ bool is_last;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q = blockIdx.y;
   const int G = gridDim.x;
@@ -193,322 +526,72 @@ __global__ void __launch_bounds__(kThreads) k_dots(VecSet V, MinState* S_, int m
     }
   }
   __syncthreads();
-  if (tid == 0) {
-    if (q < n) {
-      dd r{s_h[0], s_l[0]};
-      for (int w = 1; w < kThreads / 64; ++w) {
-        const dd o{s_h[w], s_l[w]};
-        r = isdot ? dd_add(r, o) : (dd_less(r, o) ? o : r);
-      }
-      partial[((int64_t)q * G + blockIdx.x) * 2] = r.h;
-      partial[((int64_t)q * G + blockIdx.x) * 2 + 1] = r.l;
+  if (tid == 0 && q < n) {
+    dd r{s_h[0], s_l[0]};
+    for (int w = 1; w < kThreads / 64; ++w) {
+      const dd o{s_h[w], s_l[w]};
+      r = isdot ? dd_add(r, o) : (dd_less(r, o) ? o : r);
     }
-    __threadfence();
-    is_last = atomicAdd(counter, 1u) == gridDim.x * gridDim.y - 1;
+    partial[((int64_t)q * G + blockIdx.x) * 2] = r.h;
+    partial[((int64_t)q * G + blockIdx.x) * 2 + 1] = r.l;
+  }
+}
+
+// one block: each product's range partials summed in range order (kSubs
+// sub-ranges in parallel, then the sub-range sums in order), then the
+// direction (mode 0) or the Armijo decision (mode 1)
+__global__ void __launch_bounds__(kThreads) k_dots_final(MinState* S_, MinParams P, int mode, int G,
+                                                         const double* __restrict__ partial,
+                                                         const double* __restrict__ eblk, int64_t neblk) {
+  MinState& S = *S_;
+  if (!S.running) return;
+  if (mode == 0 && S.phase != 0) return;
+  const int tid = threadIdx.x;
+  if (mode == 1) {
+    // the trial's Phi and S_max from the per-block partials of the energy pass
+    dd phi, sm;
+    double kk;
+    reduce_energy_partials(eblk, neblk, &phi, &sm, &kk);
+    if (tid == 0) {
+      S.ft[0] = phi.h;
+      S.ft[1] = phi.l;
+      S.smaxt[0] = sm.h;
+      S.smaxt[1] = sm.l;
+    }
+    __syncthreads();
+  }
+  const int k = S.k;
+  const int n = 2 * k + 2;
+  constexpr int kSubs = 7;
+  __shared__ double s_ph[kSubs][kMaxDots], s_pl[kSubs][kMaxDots];
+  {
+    const int qq = tid / kSubs, r = tid % kSubs;
+    if (qq < n) {
+      const bool dotq = !(mode == 0 && qq == 2 * k + 1);
+      const int per_r = (G + kSubs - 1) / kSubs;
+      const int b0 = r * per_r, b1 = b0 + per_r < G ? b0 + per_r : G;
+      dd acc2{0.0, 0.0};
+      for (int blk = b0; blk < b1; ++blk) {
+        const dd o{partial[((int64_t)qq * G + blk) * 2], partial[((int64_t)qq * G + blk) * 2 + 1]};
+        acc2 = dotq ? dd_add(acc2, o) : (dd_less(acc2, o) ? o : acc2);
+      }
+      s_ph[r][qq] = acc2.h;
+      s_pl[r][qq] = acc2.l;
+    }
   }
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
   if (tid < n) {
     const bool dotq = !(mode == 0 && tid == 2 * k + 1);
-    dd r{0.0, 0.0};
-    for (int blk = 0; blk < G; ++blk) {
-      const dd o{partial[((int64_t)tid * G + blk) * 2], partial[((int64_t)tid * G + blk) * 2 + 1]};
+    dd r{s_ph[0][tid], s_pl[0][tid]};
+    for (int q2 = 1; q2 < kSubs; ++q2) {
+      const dd o{s_ph[q2][tid], s_pl[q2][tid]};
       r = dotq ? dd_add(r, o) : (dd_less(r, o) ? o : r);
     }
     st(mode == 0 ? S.dir_dots[tid] : S.trial_dots[tid], r);
   }
-  if (tid == 0) *counter = 0u;
-}
-
-// ---------------------------------------------------------------------------
-// one wave: the direction.  Compact form with H0 = gamma I:
-//   H g = gamma g + S top - gamma Y z,  R z = u,  R^T top = D z + gamma (Y^T Y z - w)
-// with u = S^T g, w = Y^T g, R the upper triangle of S^T Y and D its diagonal.
-// Lane i holds row i; the triangular solves run column by column.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_direction(MinState* S_, MinParams P) {
-  MinState& S = *S_;
-  if (!S.running || S.phase != 0) {
-    if (threadIdx.x == 0) S.new_dir = 0;
-    return;
-  }
-  const int i = threadIdx.x;
-  const int k = S.k;
-  const dd gg = ld(S.dir_dots[2 * k]);
-  const dd gmax = ld(S.dir_dots[2 * k + 1]);
-  bool use_sd = (k == 0);
-  dd gp{0.0, 0.0};
-  if (!use_sd) {
-    const dd gamma = dd_div(ld(S.SY[k - 1][k - 1]), ld(S.YY[k - 1][k - 1]));
-    // back substitution R z = u, column by column (rows i < j updated with z_j)
-    dd acc = i < k ? ld(S.dir_dots[i]) : dd{0.0, 0.0};
-    dd zi{0.0, 0.0};
-    for (int j = k - 1; j >= 0; --j) {
-      if (i == j) zi = dd_div(acc, ld(S.SY[j][j]));
-      const dd zj = shfl_dd(zi, j);
-      if (i < j) acc = dd_sub(acc, dd_mul(ld(S.SY[i][j]), zj));
-    }
-    // rhs_i = D_i z_i + gamma (sum_j YY_ij z_j - w_i)
-    dd rhs{0.0, 0.0};
-    dd t{0.0, 0.0};
-    for (int j = 0; j < k; ++j) {
-      const dd zj = shfl_dd(zi, j);
-      if (i < k) t = dd_add(t, dd_mul(ld(S.YY[i][j]), zj));
-    }
-    if (i < k) {
-      t = dd_sub(t, ld(S.dir_dots[k + i]));
-      rhs = dd_add(dd_mul(ld(S.SY[i][i]), zi), dd_mul(gamma, t));
-    }
-    // forward substitution R^T top = rhs, column by column (rows i > j updated)
-    dd topi{0.0, 0.0};
-    acc = rhs;
-    for (int j = 0; j < k; ++j) {
-      if (i == j) topi = dd_div(acc, ld(S.SY[j][j]));
-      const dd tj = shfl_dd(topi, j);
-      if (i > j && i < k) acc = dd_sub(acc, dd_mul(ld(S.SY[j][i]), tj));
-    }
-    // coefficients; g.p = sum coef * (vector . g) in a fixed order
-    const dd cs = dd_neg(topi);       // on S[slot_i]
-    const dd cy = dd_mul(gamma, zi);  // on Y[slot_i]
-    if (i < k) {
-      st(S.coef[1 + i], cs);
-      st(S.coef[1 + k + i], cy);
-      S.coef_vec[1 + i] = 1 + S.slot[i];
-      S.coef_vec[1 + k + i] = kMaxHistory + 2 + S.slot[i];
-    }
-    gp = dd_mul(dd_neg(gamma), gg);
-    for (int j = 0; j < k; ++j) {
-      const dd a = shfl_dd(cs, j), b = shfl_dd(cy, j);
-      gp = dd_add(gp, dd_mul(a, ld(S.dir_dots[j])));
-      gp = dd_add(gp, dd_mul(b, ld(S.dir_dots[k + j])));
-    }
-    if (i == 0) {
-      st(S.coef[0], dd_neg(gamma));
-      S.coef_vec[0] = 0;
-    }
-    if (!(gp.h < 0.0 || (gp.h == 0.0 && gp.l < 0.0))) use_sd = true;
-  }
-  __syncthreads();
-  if (i != 0) return;
-  if (use_sd) {
-    S.k = 0;
-    if (gmax.h == 0.0) {  // stationary point
-      S.status = 0;
-      S.running = 0;
-      S.new_dir = 0;
-      return;
-    }
-    const dd scale = dd_div(dd{P.step, 0.0}, gmax);
-    st(S.coef[0], dd_neg(scale));
-    S.coef_vec[0] = 0;
-    S.ncoef = 1;
-    gp = dd_neg(dd_mul(scale, gg));
-  } else {
-    S.ncoef = 1 + 2 * k;
-  }
-  st(S.gp, gp);
-  S.alpha = 1.0;
-  S.halvings = 0;
-  S.phase = 1;
-  S.new_dir = 1;
-  // the candidate pair goes to a slot no kept pair uses
-  int spare = 0;
-  for (;; ++spare) {
-    bool used = false;
-    for (int h = 0; h < S.k; ++h) used |= (S.slot[h] == spare);
-    if (!used) break;
-  }
-  S.spare = spare;
-}
-
-// p <- sum_c coef_c v_c (accurate dd sums in c order)
-__global__ void __launch_bounds__(kThreads) k_lincomb(VecSet V, const MinState* S_, int64_t nv) {
-  const MinState& S = *S_;
-  if (!S.running || !S.new_dir) return;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= nv) return;
-  dd acc{0.0, 0.0};
-  for (int c = 0; c < S.ncoef; ++c) acc = dd_add(acc, dd_mul(ld(S.coef[c]), vload(vec_of(V, S.coef_vec[c]), nv, i)));
-  V.p[i] = acc.h;
-  V.p[nv + i] = acc.l;
-}
-
-// xt <- x + alpha p (alpha a power of two)
-__global__ void __launch_bounds__(kThreads) k_step(VecSet V, const MinState* S_, int64_t nv) {
-  const MinState& S = *S_;
-  if (!S.running) return;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= nv) return;
-  const double a = S.alpha;
-  const dd r = dd_add(vload(V.x, nv, i), dd{a * V.p[i], a * V.p[nv + i]});
-  V.xt[i] = r.h;
-  V.xt[nv + i] = r.l;
-}
-
-// gradient with respect to the fractional coordinates: g <- L * dPhi/dr
-__global__ void __launch_bounds__(kThreads) k_times_L(double* __restrict__ g, int64_t nv, double L,
-                                                      const int* __restrict__ active) {
-  if (active && *active == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= nv) return;
-  const dd r = dd_mul_d(dd{g[i], g[nv + i]}, L);
-  g[i] = r.h;
-  g[nv + i] = r.l;
-}
-
-// start-of-iteration tests (the top of the loop in the rules above), one thread
-__device__ void top_of_iteration(MinState& S, const MinParams& P) {
-  const int64_t it = S.iter;
-  const int W = P.W;
-  st(S.fhist[it % (2 * W)], ld(S.f));
-  if (!(S.smax[0] > P.s_floor || (S.smax[0] == P.s_floor && S.smax[1] > 0.0))) {
-    S.status = 0;
-    S.running = 0;
-    return;
-  }
-  if (it >= P.max_iter) {
-    S.status = 2;
-    S.running = 0;
-    return;
-  }
-  if (it >= 2 * (int64_t)W) {
-    dd recent = ld(S.fhist[it % (2 * W)]), older = ld(S.fhist[(it - W) % (2 * W)]);
-    for (int64_t q = it - W + 1; q <= it; ++q) {
-      const dd v = ld(S.fhist[q % (2 * W)]);
-      if (dd_less(v, recent)) recent = v;
-    }
-    for (int64_t q = it - 2 * W + 1; q <= it - W; ++q) {
-      const dd v = ld(S.fhist[q % (2 * W)]);
-      if (dd_less(v, older)) older = v;
-    }
-    if (dd_less(dd_mul_d(older, P.stall_ratio), recent)) {
-      S.status = 1;
-      S.running = 0;
-    }
-  }
-}
-
-// after the starting evaluation (f, smax set): finite check and the tests
-__global__ void k_init(MinState* S_, MinParams P) {
-  MinState& S = *S_;
-  S.iter = 0;
-  S.evals = 1;
-  S.k = 0;
-  S.phase = 0;
-  S.new_dir = 0;
-  S.accepted = 0;
-  S.ls_fail = 0;
-  S.halvings = 0;
-  S.spare = 0;
-  S.alpha = 1.0;
-  S.running = 1;
-  S.status = 2;
-  if (!isfinite(S.f[0])) {
-    S.status = 3;
-    S.running = 0;
-    return;
-  }
-  top_of_iteration(S, P);
-}
-
-// one wave: the Armijo test and its consequences
-__global__ void __launch_bounds__(64) k_decide(MinState* S_, MinParams P) {
-  MinState& S = *S_;
-  const int i = threadIdx.x;
-  __shared__ int s_push, s_drop;
-  if (!S.running) {
-    if (i == 0) S.accepted = 0;
-    return;
-  }
-  if (i == 0) {
-    S.evals += 1;
-    const dd f = ld(S.f), ft = ld(S.ft);
-    const dd bound = dd_add(f, dd_mul(dd_mul_d(dd{S.alpha, 0.0}, P.c1), ld(S.gp)));
-    s_push = 0;
-    s_drop = 0;
-    if (!dd_less(bound, ft)) {  // accepted
-      S.accepted = 1;
-      S.ls_fail = 0;
-      if (S.trial_dots[0][0] > 0.0) {
-        s_push = 1;
-        s_drop = (S.k == P.m) ? 1 : 0;
-      }
-    } else {
-      S.accepted = 0;
-      S.alpha *= 0.5;
-      S.halvings += 1;
-    }
-  }
-  __syncthreads();
-  const int k = S.k;
-  if (s_push) {
-    // drop the oldest pair when full, then append the fresh pair as the newest
-    // column of the upper triangle of S^T Y and row/column of Y^T Y
-    const int first = s_drop;
-    const int kept = k - first;
-    dd colsy{0.0, 0.0}, colyy{0.0, 0.0};
-    if (i < k) {
-      colsy = ld(S.trial_dots[2 + i]);
-      colyy = ld(S.trial_dots[2 + k + i]);
-    }
-    if (first) {
-      dd rowsy[kMaxHistory], rowyy[kMaxHistory];
-      if (i < k)
-        for (int j = 0; j < k; ++j) {
-          rowsy[j] = ld(S.SY[i][j]);
-          rowyy[j] = ld(S.YY[i][j]);
-        }
-      __syncthreads();
-      if (i >= 1 && i < k)
-        for (int j = 1; j < k; ++j) {
-          st(S.SY[i - 1][j - 1], rowsy[j]);
-          st(S.YY[i - 1][j - 1], rowyy[j]);
-        }
-    }
-    __syncthreads();
-    if (i >= first && i < k) {
-      st(S.SY[i - first][kept], colsy);
-      st(S.YY[i - first][kept], colyy);
-      st(S.YY[kept][i - first], colyy);
-    }
-    __syncthreads();
-    if (i == 0) {
-      st(S.SY[kept][kept], ld(S.trial_dots[0]));
-      st(S.YY[kept][kept], ld(S.trial_dots[1]));
-      for (int h = first; h < k; ++h) S.slot[h - first] = S.slot[h];
-      S.slot[kept] = S.spare;
-      S.k = kept + 1;
-    }
-  }
-  __syncthreads();
-  if (i != 0) return;
-  if (S.accepted) {
-    S.f[0] = S.ft[0];
-    S.f[1] = S.ft[1];
-    S.smax[0] = S.smaxt[0];
-    S.smax[1] = S.smaxt[1];
-    S.iter += 1;
-    S.phase = 0;
-    if (!isfinite(S.f[0])) {
-      S.status = 3;
-      S.running = 0;
-      return;
-    }
-    top_of_iteration(S, P);
-  } else if (S.halvings > P.max_halvings) {  // line-search failure: keep x, clear the history
-    S.ls_fail += 1;
-    S.k = 0;
-    S.iter += 1;
-    S.phase = 0;
-    if (S.ls_fail >= P.max_ls_fail) {
-      st(S.fhist[S.iter % (2 * P.W)], ld(S.f));
-      S.status = 1;
-      S.running = 0;
-      return;
-    }
-    top_of_iteration(S, P);
-  }
+  __syncthreads();  // the products written above are read by other threads below
+  if (mode == 0) direction_logic(S, P, tid);
+  else decide_logic(S, P, tid);
 }
 
 // x <- xt, g <- gt after an accepted trial
@@ -521,8 +604,6 @@ __global__ void __launch_bounds__(kThreads) k_accept(VecSet V, const MinState* S
   V.g[i] = V.gt[i];
   V.g[nv + i] = V.gt[nv + i];
 }
-
-__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 namespace {
 
@@ -538,7 +619,6 @@ struct Layout {
   VecSet V;
   MinState* state;
   double* partial;
-  unsigned int* counter;
 };
 
 void carve(char* base, int64_t nv, double* x, Layout* L) {
@@ -558,7 +638,6 @@ void carve(char* base, int64_t nv, double* x, Layout* L) {
   for (int i = 0; i <= kMaxHistory; ++i) L->V.Y[i] = (double*)take(vec);
   L->state = (MinState*)take(al256(sizeof(MinState)));
   L->partial = (double*)take(al256(sizeof(double) * 2 * kMaxDots * kDotBlocks));
-  L->counter = (unsigned int*)take(256);
 }
 
 }  // namespace
@@ -638,10 +717,8 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
     return err == SS_OK;
   };
 
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, Lay.counter);
-  ok(hipGetLastError(), "k_zero_u32");
   if (!eval(pos_dev, S->f, S->smax, V.g, nullptr)) return err;
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(1), 0, st, S, P);
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, S, P);
   ok(hipGetLastError(), "k_init");
 
   // ticks, enqueued kDepth ahead; the status word of each tick is copied to
@@ -653,16 +730,15 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
   for (int q = 0; q < kDepth && err == SS_OK; ++q) ok(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "event");
   int64_t tick = 0;
   while (err == SS_OK) {
-    hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 0, nv, Lay.partial,
-                       Lay.counter);
-    hipLaunchKernelGGL(k_direction, dim3(1), dim3(64), 0, st, S, P);
-    hipLaunchKernelGGL(k_lincomb, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
+    hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 0, nv, Lay.partial);
+    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kThreads), 0, st, S, P, 0, dot_blocks, Lay.partial, nullptr,
+                       (int64_t)0);
     hipLaunchKernelGGL(k_step, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
     if (!ok(hipGetLastError(), "direction kernels")) break;
-    if (!eval(V.xt, S->ft, S->smaxt, V.gt, running)) break;
-    hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 1, nv, Lay.partial,
-                       Lay.counter);
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, S, P);
+    if (!eval(V.xt, nullptr, nullptr, V.gt, running)) break;  // Phi_t, S_max_t: reduced in k_dots_final
+    hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 1, nv, Lay.partial);
+    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kThreads), 0, st, S, P, 1, dot_blocks, Lay.partial,
+                       (const double*)(ews + c.off_blk), c.combine_blocks);
     hipLaunchKernelGGL(k_accept, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
     if (!ok(hipGetLastError(), "decision kernels")) break;
     const int q = (int)(tick % kDepth);

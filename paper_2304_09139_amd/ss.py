@@ -165,8 +165,10 @@ class Context:
 
     KERNELS = {"nk": 0, "grad": 1, "table": 2}
 
-    def profile(self, enable: bool = True) -> None:
-        self._chk(lib().ss_profile_enable(self._h, 1 if enable else 0), "ss_profile_enable")
+    def profile(self, enable: bool = True, kernels=("nk", "grad", "table")) -> None:
+        """Turn per-launch event timing of the named kernels on (or all timing off)."""
+        mask = sum(1 << self.KERNELS[k] for k in kernels) if enable else 0
+        self._chk(lib().ss_profile_enable(self._h, mask), "ss_profile_enable")
 
     def profile_read(self, kernel: str, reset: bool = True) -> tuple[int, float]:
         """(launches, total milliseconds) of one kernel since the last reset."""
