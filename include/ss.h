@@ -132,15 +132,28 @@ int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, co
                    const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* The same evaluation with the two pair passes in plain FP64 (the first stage
+ * of a staged quench; see ss_min_opts.precision).  Same arguments, layouts and
+ * errors as ss_energy_grad; every output low word is zero.  Each term of a
+ * sum is a product of at most d + 8 (n~ pass) or d + run length (gradient
+ * pass) table entries of relative error <= 2^-53, so |C_k error| and
+ * |S_k error| are bounded by about (d + 10) N 2^-53. */
+int ss_energy_grad_fp64(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
+                        const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
+                        void* ws, size_t ws_bytes, void* stream);
+
 /* Per-kernel timing for measurement (off by default).  `mask` selects the
  * kernels: bit 0 the n~(k) pass (kernel 0), bit 1 the gradient pass (kernel 1),
  * bit 2 the phase-table kernel (kernel 2); 0 turns timing off.  Every launch of
- * a selected kernel is bracketed by hipEvents recorded on the caller's stream.
- * ss_profile_read synchronises on the recorded events and returns the number
- * of launches and their summed duration in milliseconds; reset != 0 then
- * forgets them.  SS_EINVAL for a mask outside 0..7. */
+ * a selected kernel (single or batched) is bracketed by hipEvents recorded on
+ * the caller's stream.  ss_profile_read synchronises on the recorded events and
+ * returns the number of launches, their summed duration in milliseconds and
+ * (if work != NULL) the summed work they covered: particle-wavevector pairs
+ * M N for the two passes (summed over the configurations listed in a batched
+ * launch), table entries d (R + 1) N for the table; reset != 0 then forgets
+ * them.  SS_EINVAL for a mask outside 0..7 or an unknown kernel. */
 int ss_profile_enable(ss_ctx* ctx, int mask);
-int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, double* total_ms);
+int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, double* total_ms, double* work);
 
 /* Options of the L-BFGS quench (ss_minimize).  The paper quenches with FIRE
  * until Phi is as small as the precision allows ("Simulations" section); this
@@ -149,33 +162,50 @@ int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, doubl
  *  - direction -H g by the two-loop recursion over the last `history` pairs
  *    (1..16), H0 = (s.y / y.y) I of the newest pair; with no pairs, or when
  *    that is not a descent direction, the history is cleared and the step is
- *    -g * step_cap * N^(-1/d) / max|g| (at most step_cap of the mean spacing);
+ *    -g * min(step_cap * N^(-1/d) / max|g|, 2 Phi / g.g): at most step_cap of
+ *    the mean spacing, and no longer than the step to the minimum of the
+ *    isotropic quadratic through (Phi, g) with minimum value 0 (a ground state
+ *    has Phi = 0);
  *  - Armijo backtracking from alpha = 1 by halving: accept when
  *    Phi(x + alpha p) <= Phi(x) + c1 alpha g.p; after max_halvings halvings a
  *    failure is recorded, the history cleared and x kept;
  *  - a pair (s, y) = (x_new - x, g_new - g) is kept only when s.y > 0;
  *  - stalled when min Phi over the last stall_window iterations exceeds
  *    stall_ratio * min Phi over the stall_window before, or after max_ls_fail
- *    consecutive failures; stops after max_iter iterations. */
+ *    consecutive failures; stops after max_iter iterations in all.
+ * Precision (the paper's point is that the last decades of S(k) need more than
+ * FP64, "Simulations"): 0 evaluates every energy and gradient in double-double;
+ * 1 in plain FP64 (the same sums with FP64 products and additions; S_max below
+ * about 1e-25 is then rounding noise); 2 is staged: FP64 until that stage stops
+ * (stalled, S_max <= max(s_floor, fp64_floor), or the iteration cap), then
+ * double-double from the FP64 stage's positions with the energy and gradient
+ * re-evaluated, the stall window restarted and the kept (s, y) pairs carried
+ * over (a steepest-descent restart with the capped step is far too long this
+ * close to a minimum).  The minimiser's own vectors and dot products are
+ * double-double in every mode. */
 typedef struct {
-  int32_t history;      /* 1..16 (8 is typical)   */
-  int64_t max_iter;     /* >= 0                   */
-  double s_floor;       /* stated S(k) floor      */
-  int32_t stall_window; /* >= 1, e.g. 50           */
-  double stall_ratio;   /* e.g. 0.99              */
-  double c1;            /* Armijo constant (0, 1) */
-  double step_cap;      /* > 0, e.g. 1e-2         */
-  int32_t max_halvings; /* >= 0                   */
-  int32_t max_ls_fail;  /* >= 1                   */
+  int32_t history;      /* 1..16 (8 is typical)                 */
+  int64_t max_iter;     /* >= 0                                 */
+  double s_floor;       /* stated S(k) floor                    */
+  int32_t stall_window; /* >= 1, e.g. 50                         */
+  double stall_ratio;   /* e.g. 0.99                            */
+  double c1;            /* Armijo constant (0, 1)               */
+  double step_cap;      /* > 0, e.g. 1e-2                       */
+  int32_t max_halvings; /* >= 0                                 */
+  int32_t max_ls_fail;  /* >= 1                                 */
+  int32_t precision;    /* 0 double-double, 1 FP64, 2 staged    */
+  double fp64_floor;    /* >= 0: S_max floor of the FP64 stage  */
 } ss_min_opts;
 
 /* status: 0 converged (S_max <= s_floor), 1 stalled, 2 iteration cap,
- * 3 non-finite energy */
+ * 3 non-finite energy (of the last stage run).  iters and evals count every
+ * stage; iters_fp64 is the part of iters done in FP64. */
 typedef struct {
   int32_t status;
   int64_t iters, evals, grad_evals;
   double phi[2], smax[2];
   double seconds;
+  int64_t iters_fp64;
 } ss_min_result;
 
 /* Quench pos_dev (double[2][d][N] fractional coordinates, updated in place and
@@ -185,6 +215,60 @@ typedef struct {
  * SS_ENUMERIC if the energy is not finite (status 3), or an error. */
 int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev, double* pos_dev,
                 const ss_min_opts* opts, ss_min_result* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Batches of independent quenches -------------------------------------
+ * The paper's production runs are many independent quenches from Poisson
+ * starts ("Simulations"); small configurations leave most of the GPU idle and
+ * are bound by launch latency when run one at a time.  A batch runs many
+ * quenches together: every kernel of an L-BFGS step is ONE launch whose blocks
+ * cover all configurations still running; configurations that stop leave the
+ * work lists at the next compaction.
+ *
+ * Tile shapes of the batched launches (particles per n~(k) work unit,
+ * wavevectors per gradient block) come from the context's tile table, looked up
+ * by (d, N, M) only: a configuration's reduction order -- and therefore its
+ * result, bit for bit -- is the same in every batch, alone or mixed with
+ * others.  (It may differ in the last bits from ss_minimize's result, whose
+ * launch shape is sized to fill the device with one configuration.) */
+
+/* One entry of the tile table: used for problems with d == this d (0 = any d),
+ * N <= max_N and M <= max_M; the first matching entry wins, and problems that
+ * match none use nk_chunk = 64, grad_k = 1024. */
+typedef struct {
+  int32_t d;
+  int64_t max_N, max_M;
+  int64_t nk_chunk; /* particles per n~(k) unit, >= 1 (rounded up to the LDS tile) */
+  int64_t grad_k;   /* wavevectors per gradient block, >= 1                        */
+} ss_tile;
+
+/* Replace the context's tile table by `count` entries (count = 0 clears it).
+ * Changing the table changes later batched results in their last bits; set it
+ * once, before the first batch.  SS_EINVAL for NULL with count > 0 or an entry
+ * with a non-positive size. */
+int ss_set_tiles(ss_ctx* ctx, const ss_tile* tiles, int count);
+
+/* The tile shape a problem would get (matching entry or the default). */
+int ss_get_tile(ss_ctx* ctx, const ss_problem* prob, ss_tile* out);
+
+/* Workspace bytes for ss_minimize_batch over `count` problems with per-problem
+ * options opts[i] (the history length sets the memory of each). */
+int ss_batch_workspace_size(ss_ctx* ctx, int count, const ss_problem* probs, const ss_min_opts* opts,
+                            size_t* bytes);
+
+/* Quench `count` configurations together.  probs[i], opts[i] as for
+ * ss_minimize; pos_dev[i] (double[2][d_i][N_i], fractional) is updated in
+ * place; v_dev[i] is the weight table double[2][M_i] for vkind != 0 (v_dev may
+ * be NULL when every vkind is 0).  The wavevector sets are built internally
+ * from (d_i, R2_i).  ws: ss_batch_workspace_size bytes of device memory.
+ * Batched quenches evaluate in double-double (precision must be 0).
+ * Synchronising: returns when every quench has stopped, with out[i] filled;
+ * out[i].seconds is the time from the call until the library saw quench i
+ * stop.  Returns SS_OK (individual non-finite energies show as status 3), or an
+ * error (SS_EINVAL for count < 1, NULL arrays, an invalid problem or options,
+ * or a short workspace). */
+int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs, const double* const* v_dev,
+                      double* const* pos_dev, const ss_min_opts* opts, ss_min_result* out, void* ws,
+                      size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

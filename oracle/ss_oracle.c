@@ -671,6 +671,12 @@ static int lbfgs_run(objective* o, int64_t nv, dd* x, const or_lbfgs_opts* op,
             }
             if (gmax.hi == 0.0) { status = 0; break; }
             dd scale = dd_div(dd_from(op->step_cap * nmean), gmax);
+            /* the minimum of the energy is 0 (a ground state), so the step is also
+             * bounded by 2 f / g.g, where the line along -g meets the minimum of
+             * the isotropic quadratic through (f, g) */
+            dd polyak = dd_div(dd_mul_d(f, 2.0), vdot(nv, g, g));
+            if (dd_lt(polyak, scale)) scale = polyak;
+            if (scale.hi == 0.0) { status = 0; break; }
             for (int64_t i = 0; i < nv; i++) p[i] = dd_neg(dd_mul(g[i], scale));
             gp = vdot(nv, g, p);
         }

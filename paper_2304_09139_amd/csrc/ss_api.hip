@@ -17,10 +17,21 @@ namespace ss {
 hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab, hipStream_t st,
                         const int* active);
 hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units, int64_t nunits,
-                     const double* tab, double* part, hipStream_t st, const int* active);
+                     const double* tab, double* part, const SlotOffsets& so, hipStream_t st, const int* active);
 hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* rows_of,
-                             const int32_t* canon_of_lex, const double* v, double* nk_out, double* csw, double* blk,
-                             double* phi, double* smax, double* kmax, hipStream_t st, const int* active);
+                             const int32_t* k_of_slot, const int32_t* canon_of_lex, const double* v, double* nk_out,
+                             double* csw, double* blk, hipStream_t st, const int* active);
+hipError_t launch_final(const LaunchCfg& c, const double* blk, double* phi, double* smax, double* kmax, hipStream_t st,
+                        const int* active);
+hipError_t launch_nk64(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units, int64_t nunits,
+                       const double* tab, double* part, const SlotOffsets& so, hipStream_t st, const int* active);
+hipError_t launch_nk_combine64(const LaunchCfg& c, const double* part, const int32_t* rows_of,
+                               const int32_t* k_of_slot, const int32_t* canon_of_lex, const double* v,
+                               double* nk_out, double* csw, double* blk, hipStream_t st, const int* active);
+hipError_t launch_grad64(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
+                         const double* csw, double* gpart, hipStream_t st, const int* active);
+hipError_t launch_grad_combine64(const LaunchCfg& c, const double* gpart, double L, bool times_L, double* grad,
+                                 hipStream_t st, const int* active);
 hipError_t launch_grad(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
                        const double* csw, double* gpart, hipStream_t st, const int* active);
 hipError_t launch_grad_combine(const LaunchCfg& c, const double* gpart, double L, double* grad, hipStream_t st,
@@ -143,6 +154,26 @@ int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
   pl->nruns = (int64_t)runs.size();
   pl->nsegs = (int64_t)segs.size();
   pl->seg_host = segs;
+  // slot order of the n(k) partials (see SlotOffsets)
+  {
+    int64_t cnt[kSegLen] = {};
+    for (const Span& sg : segs)
+      for (int t = 0; t < sg.len; ++t) ++cnt[t];
+    int64_t acc = 0;
+    for (int t = 0; t < kSegLen; ++t) {
+      pl->slot_off.off[t] = (int32_t)acc;
+      acc += cnt[t];
+    }
+    if (acc != M) return set_err(ctx, SS_EHIP, "piece slots do not cover the wavevectors");
+    std::vector<int32_t> kos((size_t)M, -1);
+    for (size_t q = 0; q < segs.size(); ++q)
+      for (int t = 0; t < segs[q].len; ++t) {
+        if ((int64_t)q >= cnt[t]) return set_err(ctx, SS_EHIP, "pieces are not sorted by length");
+        kos[pl->slot_off.off[t] + q] = segs[q].k0 + t;
+      }
+    SS_HIP(ctx, hipMalloc(&pl->k_of_slot, sizeof(int32_t) * M));
+    SS_HIP(ctx, hipMemcpy(pl->k_of_slot, kos.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
+  }
   SS_HIP(ctx, hipMalloc(&pl->runs, sizeof(Span) * runs.size()));
   SS_HIP(ctx, hipMalloc(&pl->segs, sizeof(Span) * segs.size()));
   SS_HIP(ctx, hipMemcpy(pl->runs, runs.data(), sizeof(Span) * runs.size(), hipMemcpyHostToDevice));
@@ -246,7 +277,7 @@ int nk_schedule(ss_ctx* ctx, Plan* pl, int64_t N, int pt, Plan::NkSched** out) {
     maxrows = std::max(maxrows, Pb);
     const size_t s0 = b * kNkPieces, s1 = std::min(pl->seg_host.size(), s0 + kNkPieces);
     for (size_t q = s0; q < s1; ++q)
-      for (int t = 0; t < pl->seg_host[q].len; ++t) rows_of[pl->seg_host[q].k0 + t] = (int32_t)Pb;
+      for (int t = 0; t < pl->seg_host[q].len; ++t) rows_of[pl->slot_off.off[t] + q] = (int32_t)Pb;
   }
   Plan::NkSched sc;
   sc.nunits = (int64_t)units.size();
@@ -262,7 +293,39 @@ int nk_schedule(ss_ctx* ctx, Plan* pl, int64_t N, int pt, Plan::NkSched** out) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c) {
+// fixed-chunk n(k) schedule of the batched launches: every piece block gets
+// ceil(N / chunk) particle ranges of `chunk` particles (the last one shorter)
+int nk_schedule_fixed(ss_ctx* ctx, Plan* pl, int64_t N, int pt, int64_t chunk, Plan::NkSched** out) {
+  chunk = std::max<int64_t>(pt, ((chunk + pt - 1) / pt) * pt);
+  const auto key = std::make_pair(N, chunk);
+  auto it = pl->nk_fixed.find(key);
+  if (it != pl->nk_fixed.end()) {
+    *out = &it->second;
+    return SS_OK;
+  }
+  const int64_t Pb = (N + chunk - 1) / chunk;
+  const size_t nb = pl->block_maxlen.size();
+  std::vector<NkUnit> units;
+  units.reserve(nb * Pb);
+  for (size_t b = 0; b < nb; ++b)
+    for (int64_t r = 0; r < Pb; ++r)
+      units.push_back(NkUnit{(int32_t)b, (int32_t)r, (int32_t)(r * chunk), (int32_t)std::min<int64_t>(N, (r + 1) * chunk)});
+  std::vector<int32_t> rows_of(pl->M, (int32_t)Pb);
+  Plan::NkSched sc;
+  sc.nunits = (int64_t)units.size();
+  sc.rows = Pb;
+  SS_HIP(ctx, hipMalloc(&sc.units, sizeof(NkUnit) * units.size()));
+  SS_HIP(ctx, hipMalloc(&sc.rows_of, sizeof(int32_t) * rows_of.size()));
+  SS_HIP(ctx, hipMemcpy(sc.units, units.data(), sizeof(NkUnit) * units.size(), hipMemcpyHostToDevice));
+  SS_HIP(ctx, hipMemcpy(sc.rows_of, rows_of.data(), sizeof(int32_t) * rows_of.size(), hipMemcpyHostToDevice));
+  pl->nk_fixed[key] = sc;
+  *out = &pl->nk_fixed[key];
+  return SS_OK;
+}
+
+// launch shape and workspace layout; tile == nullptr: the single-launch shape
+// (grids sized to the device), else the batched shape of `tile`
+int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const TileSpec* tile = nullptr) {
   c->d = p->d;
   c->N = p->N;
   c->M = p->M;
@@ -276,16 +339,21 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c) {
   c->segblocks = (pl->nsegs + kNkPieces - 1) / kNkPieces;
   Plan::NkSched* sc = nullptr;
   {
-    int rc = nk_schedule(ctx, pl, c->N, c->pt, &sc);
+    int rc = tile ? nk_schedule_fixed(ctx, pl, c->N, c->pt, tile->nk_chunk, &sc)
+                  : nk_schedule(ctx, pl, c->N, c->pt, &sc);
     if (rc) return rc;
   }
   c->P = sc->rows;
   // gradient pass: blocks of 64 particles x Q chunks, each wave of a block on one
   // of kWaves sub-chunks of equal pair count
   const int64_t pblocks = (c->N + 63) / 64;
-  const int64_t capacity = (int64_t)num_cus(ctx) * grad_blocks_per_cu(p->d);
   const int64_t maxQ = std::min<int64_t>(std::max<int64_t>(1, pl->nruns / kWaves), 1024);
-  c->Q = (int)rounds_fit(capacity, pblocks, maxQ, 4);
+  if (tile) {
+    c->Q = (int)std::max<int64_t>(1, std::min<int64_t>(maxQ, (c->M + tile->grad_k - 1) / tile->grad_k));
+  } else {
+    const int64_t capacity = (int64_t)num_cus(ctx) * grad_blocks_per_cu(p->d);
+    c->Q = (int)rounds_fit(capacity, pblocks, maxQ, 4);
+  }
   c->combine_blocks = (c->M + kCombK - 1) / kCombK;
   size_t off = 0;
   c->off_tab = off;
@@ -323,6 +391,29 @@ int check_problem(ss_ctx* ctx, const ss_problem* p) {
 
 namespace ss {
 // shared with the minimiser
+TileSpec tile_for(ss_ctx* ctx, int d, int64_t N, int64_t M) {
+  for (const ss_tile_entry& e : ctx->tiles)
+    if ((e.d == 0 || e.d == d) && N <= e.max_N && M <= e.max_M) return e.t;
+  return TileSpec{kDefaultNkChunk, kDefaultGradK};
+}
+
+// the batched shape of a problem: plan, layout, n(k) schedule and gradient chunks
+int prepare_tiled(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg, Plan::NkSched** sc,
+                  int32_t** chunk_begin) {
+  int rc = check_problem(ctx, p);
+  if (rc) return rc;
+  SS_HIP(ctx, hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> g(ctx->mu);
+  rc = build_plan(ctx, p->d, p->R2, pl);
+  if (rc) return rc;
+  const TileSpec t = tile_for(ctx, p->d, p->N, p->M);
+  rc = make_cfg(ctx, p, *pl, cfg, &t);
+  if (rc) return rc;
+  rc = nk_schedule_fixed(ctx, *pl, p->N, cfg->pt, t.nk_chunk, sc);
+  if (rc) return rc;
+  return chunk_bounds(ctx, *pl, cfg->Q * kWaves, chunk_begin);
+}
+
 int prepare(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg) {
   int rc = check_problem(ctx, p);
   if (rc) return rc;
@@ -344,22 +435,31 @@ hipEvent_t prof_event(ss_ctx* ctx) {
   }
   return e;
 }
-// records an event pair around `launch` on `st` when profiling is enabled
-template <class F>
-hipError_t timed(ss_ctx* ctx, int which, hipStream_t st, F launch) {
-  if (!(ctx->prof.mask & (1 << which))) return launch();
-  hipEvent_t a = prof_event(ctx), b = prof_event(ctx);
-  if (a) hipEventRecord(a, st);
-  hipError_t e = launch();
-  if (b) hipEventRecord(b, st);
-  if (a && b) ctx->prof.ev[which].push_back({a, b});
-  return e;
-}
 }  // namespace
+
+hipEvent_t prof_begin(ss_ctx* ctx, int which, hipStream_t st) {
+  if (!(ctx->prof.mask & (1 << which))) return nullptr;
+  hipEvent_t a = prof_event(ctx);
+  if (a && hipEventRecord(a, st) != hipSuccess) {
+    ctx->prof.pool.push_back(a);
+    return nullptr;
+  }
+  return a;
+}
+
+void prof_end(ss_ctx* ctx, int which, hipStream_t st, hipEvent_t a, double work) {
+  hipEvent_t b = prof_event(ctx);
+  if (!b || hipEventRecord(b, st) != hipSuccess) {
+    ctx->prof.pool.push_back(a);
+    if (b) ctx->prof.pool.push_back(b);
+    return;
+  }
+  ctx->prof.ev[which].push_back(ProfileLog::Rec{a, b, work});
+}
 
 int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg& c, const double* v_dev,
                      const double* pos, double* phi, double* smax, double* grad, double* nk, char* ws,
-                     hipStream_t st, double* kmax, const int* active) {
+                     hipStream_t st, double* kmax, const int* active, bool fp64) {
   double* tab = (double*)(ws + c.off_tab);
   double* part = (double*)(ws + c.off_part);
   double* csw = (double*)(ws + c.off_csw);
@@ -367,11 +467,19 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
   double* blk = (double*)(ws + c.off_blk);
   double* scal = (double*)(ws + c.off_scalar);
   const double* v = p->vkind == 0 ? nullptr : v_dev;
-  SS_HIP(ctx, timed(ctx, 2, st, [&] { return launch_table(pos, p->d, p->N, c.R1, tab, st, active); }));
+  const double pairs = (double)p->M * (double)p->N;
+  SS_HIP(ctx, timed(ctx, 2, st, (double)p->d * c.R1 * p->N,
+                    [&] { return launch_table(pos, p->d, p->N, c.R1, tab, st, active); }));
   Plan::NkSched* sc = &pl->nk_sched.at(p->N);
-  SS_HIP(ctx, timed(ctx, 0, st, [&] { return launch_nk(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, st, active); }));
-  SS_HIP(ctx, launch_nk_combine(c, part, sc->rows_of, pl->canon_of_lex, v, nk, csw, blk, phi,
-                                smax ? smax : scal + 2, kmax, st, active));
+  SS_HIP(ctx, timed(ctx, 0, st, pairs, [&] {
+           return fp64 ? launch_nk64(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active)
+                       : launch_nk(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active);
+         }));
+  if (fp64)
+    SS_HIP(ctx, launch_nk_combine64(c, part, sc->rows_of, pl->k_of_slot, pl->canon_of_lex, v, nk, csw, blk, st, active));
+  else
+    SS_HIP(ctx, launch_nk_combine(c, part, sc->rows_of, pl->k_of_slot, pl->canon_of_lex, v, nk, csw, blk, st, active));
+  if (phi) SS_HIP(ctx, launch_final(c, blk, phi, smax ? smax : scal + 2, kmax, st, active));
   if (grad) {
     int32_t* cb = nullptr;
     {
@@ -379,8 +487,12 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
       int rc = chunk_bounds(ctx, pl, c.Q * kWaves, &cb);
       if (rc) return rc;
     }
-    SS_HIP(ctx, timed(ctx, 1, st, [&] { return launch_grad(c, pl->runs, cb, tab, csw, gpart, st, active); }));
-    SS_HIP(ctx, launch_grad_combine(c, gpart, p->L, grad, st, active));
+    SS_HIP(ctx, timed(ctx, 1, st, pairs, [&] {
+             return fp64 ? launch_grad64(c, pl->runs, cb, tab, csw, gpart, st, active)
+                         : launch_grad(c, pl->runs, cb, tab, csw, gpart, st, active);
+           }));
+    if (fp64) SS_HIP(ctx, launch_grad_combine64(c, gpart, p->L, false, grad, st, active));
+    else SS_HIP(ctx, launch_grad_combine(c, gpart, p->L, grad, st, active));
   }
   return SS_OK;
 }
@@ -415,7 +527,12 @@ int ss_destroy(ss_ctx* ctx) {
     hipFree(pl->canon_of_lex);
     hipFree(pl->runs);
     hipFree(pl->segs);
+    hipFree(pl->k_of_slot);
     for (auto& cb : pl->chunk_begin) hipFree(cb.second);
+    for (auto& ns : pl->nk_fixed) {
+      hipFree(ns.second.units);
+      hipFree(ns.second.rows_of);
+    }
     for (auto& ns : pl->nk_sched) {
       hipFree(ns.second.units);
       hipFree(ns.second.rows_of);
@@ -424,8 +541,8 @@ int ss_destroy(ss_ctx* ctx) {
   }
   for (auto& v : ctx->prof.ev)
     for (auto& pr : v) {
-      hipEventDestroy(pr.first);
-      hipEventDestroy(pr.second);
+      hipEventDestroy(pr.a);
+      hipEventDestroy(pr.b);
     }
   for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
   if (ctx->build_stream) hipStreamDestroy(ctx->build_stream);
@@ -527,32 +644,34 @@ int ss_profile_enable(ss_ctx* ctx, int mask) {
   return SS_OK;
 }
 
-int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, double* total_ms) {
+int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, double* total_ms, double* work) {
   if (!ctx || !launches || !total_ms || kernel < 0 || kernel > 2) return SS_EINVAL;
   std::lock_guard<std::mutex> g(ctx->mu);
   auto& v = ctx->prof.ev[kernel];
-  double tot = 0.0;
+  double tot = 0.0, wk = 0.0;
   for (auto& pr : v) {
-    SS_HIP(ctx, hipEventSynchronize(pr.second));
+    SS_HIP(ctx, hipEventSynchronize(pr.b));
     float ms = 0.0f;
-    SS_HIP(ctx, hipEventElapsedTime(&ms, pr.first, pr.second));
+    SS_HIP(ctx, hipEventElapsedTime(&ms, pr.a, pr.b));
     tot += ms;
+    wk += pr.work;
   }
   *launches = (int64_t)v.size();
   *total_ms = tot;
+  if (work) *work = wk;
   if (reset) {
     for (auto& pr : v) {
-      ctx->prof.pool.push_back(pr.first);
-      ctx->prof.pool.push_back(pr.second);
+      ctx->prof.pool.push_back(pr.a);
+      ctx->prof.pool.push_back(pr.b);
     }
     v.clear();
   }
   return SS_OK;
 }
 
-int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
-                   const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
-                   void* ws, size_t ws_bytes, void* stream) {
+static int energy_grad_entry(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
+                             const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev,
+                             double* nk_dev, void* ws, size_t ws_bytes, void* stream, int precision) {
   if (!ctx) return SS_EINVAL;
   Plan* pl = nullptr;
   LaunchCfg c;
@@ -562,7 +681,21 @@ int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, co
   if (prob->vkind != 0 && !v_dev) return set_err(ctx, SS_EINVAL, "vkind != 0 needs v_dev");
   if (ws_bytes < c.total) return set_err(ctx, SS_EINVAL, "workspace too small");
   return energy_grad_impl(ctx, prob, pl, c, v_dev, pos_dev, phi_dev, smax_dev, grad_dev, nk_dev, (char*)ws,
-                          (hipStream_t)stream, nullptr, nullptr);
+                          (hipStream_t)stream, nullptr, nullptr, precision == 1);
+}
+
+int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
+                   const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
+                   void* ws, size_t ws_bytes, void* stream) {
+  return energy_grad_entry(ctx, prob, n_dev, v_dev, pos_dev, phi_dev, smax_dev, grad_dev, nk_dev, ws, ws_bytes,
+                           stream, 0);
+}
+
+int ss_energy_grad_fp64(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
+                        const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
+                        void* ws, size_t ws_bytes, void* stream) {
+  return energy_grad_entry(ctx, prob, n_dev, v_dev, pos_dev, phi_dev, smax_dev, grad_dev, nk_dev, ws, ws_bytes,
+                           stream, 1);
 }
 
 }  // extern "C"

@@ -1,0 +1,524 @@
+// ss_batch.hip -- many independent quenches advanced together.
+//
+// The paper's production runs are many independent quenches from Poisson
+// starts ("Simulations").  One configuration of a few thousand particles fills
+// a small part of the device, and its L-BFGS step is a chain of short launches,
+// so run one at a time the quenches are bound by launch latency.  Here every
+// kernel of a minimiser step is one launch over the blocks of all
+// configurations still running: block b of a batched launch executes block
+// units[b].idx of configuration units[b].slot's own grid (see BUnit), with the
+// same device code as the single-configuration kernels.  Each configuration's
+// launch shape comes from the tile table by (d, N, M) alone, so its results are
+// the same whatever else is in the batch.
+//
+// The host enqueues steps a few ahead, reads a per-configuration running word
+// gathered into pinned memory, and rebuilds the work lists without the
+// configurations it has seen stop (they exit at once until then).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ss.h"
+#include "ss_internal.h"
+#include "ss_min.h"
+
+namespace ss {
+int prepare_tiled(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg, Plan::NkSched** sc,
+                  int32_t** chunk_begin);
+TileSpec tile_for(ss_ctx* ctx, int d, int64_t N, int64_t M);
+bool min_opts_valid(const ss_min_opts* op);
+MinParams min_params(const ss_min_opts* op, const ss_problem* prob);
+
+hipError_t launch_batch_table(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
+                              hipStream_t st);
+hipError_t launch_batch_nk(int d, int pt, int R1max, const EvalSlot* es, const BUnit* units, int64_t n, int gate,
+                           hipStream_t st);
+hipError_t launch_batch_combine(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
+hipError_t launch_batch_final(const EvalSlot* es, const int32_t* list, int64_t n, hipStream_t st);
+hipError_t launch_batch_grad(int d, const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
+hipError_t launch_batch_gcomb(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
+                              hipStream_t st);
+hipError_t launch_batch_dots(const MinSlot* ms, const BUnit* units, int64_t n, int mode, hipStream_t st);
+hipError_t launch_batch_dots_final(const MinSlot* ms, const int32_t* list, int64_t n, int mode, hipStream_t st);
+hipError_t launch_batch_step(const MinSlot* ms, const BUnit* units, int64_t n, hipStream_t st);
+hipError_t launch_batch_accept(const MinSlot* ms, const BUnit* units, int64_t n, hipStream_t st);
+hipError_t launch_batch_init(const MinSlot* ms, const int32_t* list, int64_t n, hipStream_t st);
+hipError_t launch_batch_flags(const MinSlot* ms, const int32_t* list, int64_t n, int32_t* out, hipStream_t st);
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int dot_blocks_of(int64_t nv) { return (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (nv + 1023) / 1024)); }
+
+// minimiser memory of one configuration: g, xt, gt, p, (m + 1) S and Y vectors,
+// the state and the dot partials
+size_t min_bytes(int64_t nv, int m, int G) {
+  const size_t vec = al256(sizeof(double) * 2 * (size_t)nv);
+  return vec * (4 + 2 * (size_t)(m + 1)) + al256(sizeof(MinState)) + al256(sizeof(double) * 2 * (2 * m + 2) * G);
+}
+
+struct HostSlot {
+  ss_problem prob;
+  ss_min_opts opts;
+  Plan* pl = nullptr;
+  LaunchCfg c{};
+  Plan::NkSched* sc = nullptr;
+  int32_t* cb = nullptr;
+  int64_t nv = 0;
+  int m = 0, G = 0;
+  size_t bytes = 0;  // workspace of this configuration (energy + minimiser)
+  // unit counts of this configuration's grids
+  int64_t n_table = 0, n_nk = 0, n_comb = 0, n_grad = 0, n_gcomb = 0, n_dots = 0, n_vec = 0;
+  double work = 0.0;  // M N, for ordering
+};
+
+// offsets and counts of each batched launch inside the unit array
+struct Lists {
+  struct Group {
+    int d, pt, R1max;
+    int64_t off, n;
+    double pairs;  // M N summed over the group's configurations
+  };
+  double table_work = 0.0;
+  int64_t table_off = 0, table_n = 0, comb_off = 0, comb_n = 0, gcomb_off = 0, gcomb_n = 0;
+  int64_t dots_off = 0, dots_n = 0, vec_off = 0, vec_n = 0;
+  std::vector<Group> nk, grad;
+  int64_t nlist = 0;
+};
+
+int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot* h) {
+  int rc = prepare_tiled(ctx, p, &h->pl, &h->c, &h->sc, &h->cb);
+  if (rc) return rc;
+  if (!min_opts_valid(op)) {
+    ctx->last_error = "invalid minimiser options";
+    return SS_EINVAL;
+  }
+  if (op->precision != 0) {
+    ctx->last_error = "batched quenches evaluate in double-double only (precision 0)";
+    return SS_EINVAL;
+  }
+  h->prob = *p;
+  h->opts = *op;
+  h->nv = (int64_t)p->d * p->N;
+  h->m = op->history;
+  h->G = dot_blocks_of(h->nv);
+  h->bytes = al256(h->c.total) + min_bytes(h->nv, h->m, h->G);
+  const int groups = (h->c.R1 + kTabRun - 1) / kTabRun;
+  h->n_table = ((int64_t)p->d * groups * p->N + kThreads - 1) / kThreads;
+  h->n_nk = h->sc->nunits;
+  h->n_comb = h->c.combine_blocks;
+  h->n_grad = ((p->N + 63) / 64) * h->c.Q;
+  h->n_gcomb = (h->nv + kThreads - 1) / kThreads;
+  h->n_dots = (int64_t)h->G * (2 * h->m + 2);
+  h->n_vec = (h->nv + kThreads - 1) / kThreads;
+  h->work = (double)p->M * (double)p->N;
+  return SS_OK;
+}
+
+// work lists of the configurations in `active` (largest first within every launch)
+void build_lists(const std::vector<HostSlot>& hs, std::vector<int> active, std::vector<BUnit>& U,
+                 std::vector<int32_t>& list, Lists& L) {
+  std::stable_sort(active.begin(), active.end(), [&](int a, int b) { return hs[a].work > hs[b].work; });
+  U.clear();
+  list.assign(active.begin(), active.end());
+  L = Lists();
+  L.nlist = (int64_t)list.size();
+  auto add = [&](int64_t n_of_slot, int s) {
+    for (int64_t i = 0; i < n_of_slot; ++i) U.push_back(BUnit{(int32_t)s, (int32_t)i});
+  };
+  L.table_off = (int64_t)U.size();
+  for (int s : active) {
+    add(hs[s].n_table, s);
+    L.table_work += (double)hs[s].prob.d * hs[s].c.R1 * hs[s].prob.N;
+  }
+  L.table_n = (int64_t)U.size() - L.table_off;
+  // n(k) pass grouped by (d, LDS tile)
+  for (int d = 1; d <= 4; ++d)
+    for (int pt : {16, 4, 1}) {
+      Lists::Group g{d, pt, 0, (int64_t)U.size(), 0, 0.0};
+      for (int s : active)
+        if (hs[s].prob.d == d && hs[s].c.pt == pt) {
+          add(hs[s].n_nk, s);
+          g.R1max = std::max(g.R1max, hs[s].c.R1);
+          g.pairs += hs[s].work;
+        }
+      g.n = (int64_t)U.size() - g.off;
+      if (g.n > 0) L.nk.push_back(g);
+    }
+  L.comb_off = (int64_t)U.size();
+  for (int s : active) add(hs[s].n_comb, s);
+  L.comb_n = (int64_t)U.size() - L.comb_off;
+  for (int d = 1; d <= 4; ++d) {
+    Lists::Group g{d, 0, 0, (int64_t)U.size(), 0, 0.0};
+    for (int s : active)
+      if (hs[s].prob.d == d) {
+        add(hs[s].n_grad, s);
+        g.pairs += hs[s].work;
+      }
+    g.n = (int64_t)U.size() - g.off;
+    if (g.n > 0) L.grad.push_back(g);
+  }
+  L.gcomb_off = (int64_t)U.size();
+  for (int s : active) add(hs[s].n_gcomb, s);
+  L.gcomb_n = (int64_t)U.size() - L.gcomb_off;
+  L.dots_off = (int64_t)U.size();
+  for (int s : active) add(hs[s].n_dots, s);
+  L.dots_n = (int64_t)U.size() - L.dots_off;
+  L.vec_off = (int64_t)U.size();
+  for (int s : active) add(hs[s].n_vec, s);
+  L.vec_n = (int64_t)U.size() - L.vec_off;
+}
+
+// device-side header of the batch workspace
+struct Header {
+  EvalSlot* es;
+  MinSlot* ms;
+  BUnit* units;
+  int32_t* list;
+  int32_t* flags;
+  size_t bytes;
+};
+
+// byte offsets of the header parts: es, ms, units, list, flags, end
+void header_offsets(int count, int64_t ucap, size_t off[6]) {
+  off[0] = 0;
+  off[1] = off[0] + al256(sizeof(EvalSlot) * count);
+  off[2] = off[1] + al256(sizeof(MinSlot) * count);
+  off[3] = off[2] + al256(sizeof(BUnit) * (size_t)std::max<int64_t>(ucap, 1));
+  off[4] = off[3] + al256(sizeof(int32_t) * count);
+  off[5] = off[4] + al256(sizeof(int32_t) * count);
+}
+
+Header carve_header(char* base, int count, int64_t ucap) {
+  size_t off[6];
+  header_offsets(count, ucap, off);
+  Header h;
+  h.es = (EvalSlot*)(base + off[0]);
+  h.ms = (MinSlot*)(base + off[1]);
+  h.units = (BUnit*)(base + off[2]);
+  h.list = (int32_t*)(base + off[3]);
+  h.flags = (int32_t*)(base + off[4]);
+  h.bytes = off[5];
+  return h;
+}
+
+void fill_slot(const HostSlot& h, char* mem, double* x, const double* v, EvalSlot* E, MinSlot* C) {
+  const LaunchCfg& c = h.c;
+  memset(E, 0, sizeof(*E));
+  memset(C, 0, sizeof(*C));
+  E->d = h.prob.d;
+  E->R1 = c.R1;
+  E->Q = c.Q;
+  E->pt = c.pt;
+  E->N = h.prob.N;
+  E->M = h.prob.M;
+  E->nsegs = h.pl->nsegs;
+  E->combine_blocks = c.combine_blocks;
+  E->pblocks = (h.prob.N + 63) / 64;
+  E->L = h.prob.L;
+  E->segs = h.pl->segs;
+  E->units = h.sc->units;
+  E->rows_of = h.sc->rows_of;
+  E->k_of_slot = h.pl->k_of_slot;
+  E->runs = h.pl->runs;
+  E->chunk_begin = h.cb;
+  E->canon_of_lex = h.pl->canon_of_lex;
+  E->v = h.prob.vkind == 0 ? nullptr : v;
+  E->so = h.pl->slot_off;
+  E->tab = (double*)(mem + c.off_tab);
+  E->part = (double*)(mem + c.off_part);
+  E->csw = (double*)(mem + c.off_csw);
+  E->gpart = (double*)(mem + c.off_gpart);
+  E->blk = (double*)(mem + c.off_blk);
+  // minimiser memory
+  const size_t vec = al256(sizeof(double) * 2 * (size_t)h.nv);
+  char* p = mem + al256(c.total);
+  auto take = [&](size_t n) {
+    char* r = p;
+    p += n;
+    return r;
+  };
+  VecSet& V = C->V;
+  V.x = x;
+  V.g = (double*)take(vec);
+  V.xt = (double*)take(vec);
+  V.gt = (double*)take(vec);
+  V.p = (double*)take(vec);
+  for (int i = 0; i <= h.m; ++i) V.S[i] = (double*)take(vec);
+  for (int i = 0; i <= h.m; ++i) V.Y[i] = (double*)take(vec);
+  C->S = (MinState*)take(al256(sizeof(MinState)));
+  C->partial = (double*)take(al256(sizeof(double) * 2 * (2 * h.m + 2) * h.G));
+  C->P = min_params(&h.opts, &h.prob);
+  C->eblk = E->blk;
+  C->neblk = c.combine_blocks;
+  C->nv = h.nv;
+  C->dot_blocks = h.G;
+  E->pos[0] = V.x;
+  E->pos[1] = V.xt;
+  E->grad[0] = V.g;
+  E->grad[1] = V.gt;
+  E->phi = C->S->f;
+  E->smax = C->S->smax;
+  E->running = &C->S->running;
+}
+
+struct Pinned {
+  void* p = nullptr;
+  ~Pinned() {
+    if (p) hipHostFree(p);
+  }
+};
+
+int setup_all(ss_ctx* ctx, int count, const ss_problem* probs, const ss_min_opts* opts, std::vector<HostSlot>& hs,
+              int64_t* ucap, size_t* total) {
+  if (!ctx) return SS_EINVAL;
+  if (count < 1 || !probs || !opts) {
+    ctx->last_error = "count < 1 or NULL problem/option arrays";
+    return SS_EINVAL;
+  }
+  hs.assign(count, HostSlot());
+  for (int i = 0; i < count; ++i) {
+    int rc = setup_slot(ctx, &probs[i], &opts[i], &hs[i]);
+    if (rc) {
+      ctx->last_error = "configuration " + std::to_string(i) + ": " + ctx->last_error;
+      return rc;
+    }
+  }
+  std::vector<int> all(count);
+  std::iota(all.begin(), all.end(), 0);
+  std::vector<BUnit> U;
+  std::vector<int32_t> list;
+  Lists L;
+  build_lists(hs, all, U, list, L);
+  if ((int64_t)U.size() >= ((int64_t)1 << 31)) {
+    ctx->last_error = "batch too large for one launch";
+    return SS_EINVAL;
+  }
+  *ucap = (int64_t)U.size();
+  size_t hoff[6];
+  header_offsets(count, *ucap, hoff);
+  size_t t = hoff[5];
+  for (const HostSlot& h : hs) t += h.bytes;
+  *total = t;
+  return SS_OK;
+}
+
+}  // namespace
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" int ss_set_tiles(ss_ctx* ctx, const ss_tile* tiles, int count) {
+  if (!ctx || count < 0 || (count > 0 && !tiles)) return SS_EINVAL;
+  std::vector<ss_tile_entry> t;
+  for (int i = 0; i < count; ++i) {
+    const ss_tile& e = tiles[i];
+    if (e.d < 0 || e.d > 4 || e.nk_chunk < 1 || e.grad_k < 1 || e.max_N < 1 || e.max_M < 1) {
+      ctx->last_error = "invalid tile entry " + std::to_string(i);
+      return SS_EINVAL;
+    }
+    t.push_back(ss_tile_entry{e.d, e.max_N, e.max_M, TileSpec{e.nk_chunk, e.grad_k}});
+  }
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->tiles = t;
+  return SS_OK;
+}
+
+extern "C" int ss_get_tile(ss_ctx* ctx, const ss_problem* prob, ss_tile* out) {
+  if (!ctx || !prob || !out) return SS_EINVAL;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  const TileSpec t = tile_for(ctx, prob->d, prob->N, prob->M);
+  out->d = prob->d;
+  out->max_N = prob->N;
+  out->max_M = prob->M;
+  out->nk_chunk = t.nk_chunk;
+  out->grad_k = t.grad_k;
+  return SS_OK;
+}
+
+extern "C" int ss_batch_workspace_size(ss_ctx* ctx, int count, const ss_problem* probs, const ss_min_opts* opts,
+                                       size_t* bytes) {
+  if (!ctx || !bytes) return SS_EINVAL;
+  std::vector<HostSlot> hs;
+  int64_t ucap = 0;
+  return setup_all(ctx, count, probs, opts, hs, &ucap, bytes);
+}
+
+extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs, const double* const* v_dev,
+                                 double* const* pos_dev, const ss_min_opts* opts, ss_min_result* out, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  if (!ctx) return SS_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<HostSlot> hs;
+  int64_t ucap = 0;
+  size_t need = 0;
+  int rc = setup_all(ctx, count, probs, opts, hs, &ucap, &need);
+  if (rc) return rc;
+  if (!pos_dev || !out || !ws) {
+    ctx->last_error = "NULL required pointer";
+    return SS_EINVAL;
+  }
+  for (int i = 0; i < count; ++i) {
+    if (!pos_dev[i]) {
+      ctx->last_error = "pos_dev[" + std::to_string(i) + "] is NULL";
+      return SS_EINVAL;
+    }
+    if (probs[i].vkind != 0 && (!v_dev || !v_dev[i])) {
+      ctx->last_error = "configuration " + std::to_string(i) + ": vkind != 0 needs v_dev";
+      return SS_EINVAL;
+    }
+  }
+  if (ws_bytes < need) {
+    ctx->last_error = "workspace too small";
+    return SS_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  const Header H = carve_header(base, count, ucap);
+  std::vector<EvalSlot> es(count);
+  std::vector<MinSlot> ms(count);
+  {
+    size_t off = H.bytes;
+    for (int i = 0; i < count; ++i) {
+      fill_slot(hs[i], base + off, pos_dev[i], v_dev ? v_dev[i] : nullptr, &es[i], &ms[i]);
+      off += hs[i].bytes;
+    }
+  }
+  int err = SS_OK;
+  auto ok = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && err == SS_OK) {
+      ctx->last_error = std::string(what) + ": " + hipGetErrorString(e);
+      err = e == hipErrorOutOfMemory ? SS_ENOMEM : SS_EHIP;
+    }
+    return err == SS_OK;
+  };
+  constexpr int kDepth = 3;
+  // pinned staging: descriptors, unit lists, flag ring, final states
+  const size_t desc_bytes = sizeof(EvalSlot) * count + sizeof(MinSlot) * count;
+  const size_t list_bytes = sizeof(BUnit) * (size_t)std::max<int64_t>(ucap, 1) + sizeof(int32_t) * count;
+  Pinned pin_desc, pin_list, pin_flags, pin_state;
+  if (!ok(hipHostMalloc(&pin_desc.p, desc_bytes, hipHostMallocDefault), "hipHostMalloc")) return err;
+  if (!ok(hipHostMalloc(&pin_list.p, list_bytes, hipHostMallocDefault), "hipHostMalloc")) return err;
+  if (!ok(hipHostMalloc(&pin_flags.p, sizeof(int32_t) * count * kDepth, hipHostMallocDefault), "hipHostMalloc"))
+    return err;
+  if (!ok(hipHostMalloc(&pin_state.p, sizeof(MinState) * count, hipHostMallocDefault), "hipHostMalloc")) return err;
+  memcpy(pin_desc.p, es.data(), sizeof(EvalSlot) * count);
+  memcpy((char*)pin_desc.p + sizeof(EvalSlot) * count, ms.data(), sizeof(MinSlot) * count);
+  ok(hipMemcpyAsync(H.es, pin_desc.p, sizeof(EvalSlot) * count, hipMemcpyHostToDevice, st), "descriptor copy");
+  ok(hipMemcpyAsync(H.ms, (char*)pin_desc.p + sizeof(EvalSlot) * count, sizeof(MinSlot) * count,
+                    hipMemcpyHostToDevice, st),
+     "descriptor copy");
+
+  hipEvent_t ev[kDepth] = {}, ev_up = nullptr;
+  for (int q = 0; q < kDepth && err == SS_OK; ++q) ok(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "event");
+  ok(hipEventCreateWithFlags(&ev_up, hipEventDisableTiming), "event");
+  bool up_pending = false;
+
+  std::vector<BUnit> U;
+  std::vector<int32_t> list;
+  Lists L;
+  auto upload = [&](const std::vector<int>& active) {
+    build_lists(hs, active, U, list, L);
+    if (up_pending && !ok(hipEventSynchronize(ev_up), "event sync")) return false;
+    memcpy(pin_list.p, U.data(), sizeof(BUnit) * U.size());
+    memcpy((char*)pin_list.p + sizeof(BUnit) * ucap, list.data(), sizeof(int32_t) * list.size());
+    if (!U.empty()) ok(hipMemcpyAsync(H.units, pin_list.p, sizeof(BUnit) * U.size(), hipMemcpyHostToDevice, st), "list copy");
+    ok(hipMemcpyAsync(H.list, (char*)pin_list.p + sizeof(BUnit) * ucap, sizeof(int32_t) * list.size(),
+                      hipMemcpyHostToDevice, st),
+       "list copy");
+    ok(hipEventRecord(ev_up, st), "event record");
+    up_pending = true;
+    return err == SS_OK;
+  };
+  auto eval = [&](int which, int gate) {
+    ok(timed(ctx, 2, st, L.table_work,
+             [&] { return launch_batch_table(H.es, H.units + L.table_off, L.table_n, which, gate, st); }),
+       "batched table");
+    for (const auto& g : L.nk)
+      ok(timed(ctx, 0, st, g.pairs,
+               [&] { return launch_batch_nk(g.d, g.pt, g.R1max, H.es, H.units + g.off, g.n, gate, st); }),
+         "batched n(k)");
+    ok(launch_batch_combine(H.es, H.units + L.comb_off, L.comb_n, gate, st), "batched combine");
+    for (const auto& g : L.grad)
+      ok(timed(ctx, 1, st, g.pairs, [&] { return launch_batch_grad(g.d, H.es, H.units + g.off, g.n, gate, st); }),
+         "batched gradient");
+    ok(launch_batch_gcomb(H.es, H.units + L.gcomb_off, L.gcomb_n, which, gate, st), "batched gradient combine");
+    return err == SS_OK;
+  };
+
+  std::vector<int> active(count);
+  std::iota(active.begin(), active.end(), 0);
+  std::vector<double> t_stop(count, -1.0);
+  // the starting evaluation and the first tests of every configuration
+  if (upload(active) && eval(0, 0)) {
+    ok(launch_batch_final(H.es, H.list, L.nlist, st), "batched final");
+    ok(launch_batch_init(H.ms, H.list, L.nlist, st), "batched init");
+  }
+  int64_t tick = 0;
+  while (err == SS_OK) {
+    ok(launch_batch_dots(H.ms, H.units + L.dots_off, L.dots_n, 0, st), "batched dots");
+    ok(launch_batch_dots_final(H.ms, H.list, L.nlist, 0, st), "batched direction");
+    ok(launch_batch_step(H.ms, H.units + L.vec_off, L.vec_n, st), "batched step");
+    if (!eval(1, 1)) break;
+    ok(launch_batch_dots(H.ms, H.units + L.dots_off, L.dots_n, 1, st), "batched dots");
+    ok(launch_batch_dots_final(H.ms, H.list, L.nlist, 1, st), "batched decision");
+    ok(launch_batch_accept(H.ms, H.units + L.vec_off, L.vec_n, st), "batched accept");
+    ok(launch_batch_flags(H.ms, H.list, L.nlist, H.flags, st), "batched flags");
+    const int q = (int)(tick % kDepth);
+    int32_t* hf = (int32_t*)pin_flags.p + (size_t)q * count;
+    if (!ok(hipMemcpyAsync(hf, H.flags, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st), "flag copy")) break;
+    if (!ok(hipEventRecord(ev[q], st), "event record")) break;
+    ++tick;
+    if (tick < kDepth) continue;
+    const int w = (int)(tick % kDepth);  // the oldest step in flight
+    if (!ok(hipEventSynchronize(ev[w]), "event sync")) break;
+    const int32_t* f = (int32_t*)pin_flags.p + (size_t)w * count;
+    // the flags of step tick - kDepth cover the configurations listed then,
+    // which include every configuration listed now
+    std::vector<int> still;
+    const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int s : active) {
+      if (f[s]) still.push_back(s);
+      else if (t_stop[s] < 0.0) t_stop[s] = now;
+    }
+    if (still.empty()) break;
+    if (still.size() < active.size()) {
+      active = still;
+      if (!upload(active)) break;
+    }
+  }
+  ok(hipStreamSynchronize(st), "final sync");
+  if (err == SS_OK) {
+    for (int i = 0; i < count; ++i)
+      ok(hipMemcpyAsync((MinState*)pin_state.p + i, ms[i].S, sizeof(MinState), hipMemcpyDeviceToHost, st),
+         "state copy");
+    ok(hipStreamSynchronize(st), "state sync");
+  }
+  for (int q = 0; q < kDepth; ++q)
+    if (ev[q]) hipEventDestroy(ev[q]);
+  if (ev_up) hipEventDestroy(ev_up);
+  if (err != SS_OK) return err;
+  const double end = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < count; ++i) {
+    const MinState& hs_ = ((MinState*)pin_state.p)[i];
+    out[i].status = hs_.status;
+    out[i].iters = hs_.iter;
+    out[i].evals = hs_.evals;
+    out[i].grad_evals = hs_.evals;
+    out[i].phi[0] = hs_.f[0];
+    out[i].phi[1] = hs_.f[1];
+    out[i].smax[0] = hs_.smax[0];
+    out[i].smax[1] = hs_.smax[1];
+    out[i].seconds = t_stop[i] >= 0.0 ? t_stop[i] : end;
+    out[i].iters_fp64 = 0;
+  }
+  return SS_OK;
+}

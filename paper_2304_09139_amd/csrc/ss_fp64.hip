@@ -1,0 +1,312 @@
+// ss_fp64.hip -- the two pair passes in plain FP64 arithmetic, for the first
+// stage of a staged quench.
+//
+// The paper's point is that the last decades of S(k) need double-double; the
+// early part of a quench from a Poisson start does not.  These kernels compute
+// the same sums as the double-double passes (n~(k), Phi, S_max and the
+// gradient, by the same factorisation exp(2 pi i n.u) = prod_a z_a^{n_a} over
+// the same runs and pieces) with FP64 products and sums: about a fifth of the
+// operations per pair.  The phase table is the double-double one; only its
+// high words are read.  Results are written in the double-double layouts with
+// zero low words, so the minimiser is unchanged.
+//
+// Error: every table entry carries a relative error <= 2^-53; a term is a
+// product of at most D - 1 + len of them (len <= kSegLen in the n(k) pass, the
+// run length in the gradient pass), so |term error| <= (D + len + 1) 2^-53 and
+// the N-term sums add N rounding errors of their own.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ss_dd.h"
+#include "ss_internal.h"
+
+namespace ss {
+
+struct c64 {
+  double re, im;
+};
+
+__device__ __forceinline__ c64 cmul64(c64 a, c64 b) {
+  return c64{__builtin_fma(a.re, b.re, -(a.im * b.im)), __builtin_fma(a.re, b.im, a.im * b.re)};
+}
+
+// entry z_a^m (high words) of a particle table staged in LDS as [a][m][re, im]
+__device__ __forceinline__ c64 lds64_entry(const double* tp, int R1, int a, int m) {
+  const int mm = m < 0 ? -m : m;
+  const double* e = tp + (a * R1 + mm) * 2;
+  return c64{e[0], m < 0 ? -e[1] : e[1]};
+}
+
+// n~(k) partials in FP64: part[(row * 2 + c) * M + slot], c = (C, S), slot order
+template <int D, int PT>
+__global__ void __launch_bounds__(kThreads) k_nk64(const Span* __restrict__ segs, int64_t nseg,
+                                                   const NkUnit* __restrict__ units, const double* __restrict__ tab,
+                                                   int64_t N, int R1, double* __restrict__ part, int64_t M,
+                                                   const SlotOffsets so, const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  extern __shared__ double lds[];  // [PT][D][R1][2]
+  const int tid = threadIdx.x;
+  const NkUnit u = units[blockIdx.x];
+  const int64_t s = (int64_t)u.block * kNkPieces + tid;
+  const Span sg = segs[s < nseg ? s : nseg - 1];
+  const int len = s < nseg ? sg.len : 0;
+  const int epp = D * R1 * 2;  // doubles per particle
+  double cr[kSegLen], ci[kSegLen];
+#pragma unroll
+  for (int t = 0; t < kSegLen; ++t) cr[t] = ci[t] = 0.0;
+  for (int64_t tile = u.j0; tile < u.j1; tile += PT) {
+    const int np = (int)((u.j1 - tile) < PT ? (u.j1 - tile) : PT);
+    __syncthreads();
+    for (int i = tid; i < epp * PT; i += kThreads) {
+      const int p = i % PT;
+      const int ec = i / PT;  // (a R1 + m) * 2 + part; part 0 = re.hi (row 0), 1 = im.hi (row 2)
+      const int64_t row = (int64_t)(ec >> 1) * 4 + 2 * (ec & 1);
+      lds[p * epp + ec] = p < np ? tab[row * N + tile + p] : 0.0;
+    }
+    __syncthreads();
+    if (len > 0) {
+      for (int p = 0; p < np; ++p) {
+        const double* tp = lds + p * epp;
+        c64 w = lds64_entry(tp, R1, D - 1, sg.n[D - 1]);
+#pragma unroll
+        for (int a = 0; a < D - 1; ++a) w = cmul64(w, lds64_entry(tp, R1, a, sg.n[a]));
+        const c64 z = lds64_entry(tp, R1, D - 1, 1);
+#pragma unroll
+        for (int t = 0; t < kSegLen; ++t) {
+          if (t < len) {
+            cr[t] += w.re;
+            ci[t] += w.im;
+            if (t + 1 < len) w = cmul64(w, z);
+          }
+        }
+      }
+    }
+  }
+  double* out = part + (int64_t)u.row * 2 * M;
+#pragma unroll
+  for (int t = 0; t < kSegLen; ++t) {
+    if (t < len) {
+      const int64_t slot = so.off[t] + s;
+      out[slot] = cr[t];
+      out[M + slot] = ci[t];
+    }
+  }
+}
+
+// combine the FP64 partials (fixed order); n~ (dd layout, zero low words) in
+// canonical order, (v C, v S) in walk order as csw[2][M], and per-block Phi and
+// S_max partials in the double-double block layout
+__global__ void __launch_bounds__(kThreads) k_nk_combine64(const double* __restrict__ part,
+                                                           const int32_t* __restrict__ rows_of,
+                                                           const int32_t* __restrict__ k_of_slot, int64_t M,
+                                                           int64_t N, const int32_t* __restrict__ canon_of_lex,
+                                                           const double* __restrict__ v, double* __restrict__ nk_out,
+                                                           double* __restrict__ csw, double* __restrict__ blk,
+                                                           const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  constexpr int kCombG = kThreads / kCombK;
+  __shared__ double s_c[kCombG][2][kCombK];
+  __shared__ double s_ph[kCombK], s_mh[kCombK];
+  __shared__ int64_t s_mk[kCombK];
+  const int tid = threadIdx.x, q = tid % kCombK, g = tid / kCombK;
+  const int64_t i = (int64_t)blockIdx.x * kCombK + q;
+  double C = 0.0, S = 0.0;
+  if (i < M) {
+    const int64_t P = rows_of[i];
+    for (int64_t p = g; p < P; p += kCombG) {
+      const double* r = part + p * 2 * M;
+      C += r[i];
+      S += r[M + i];
+    }
+  }
+  s_c[g][0][q] = C;
+  s_c[g][1][q] = S;
+  __syncthreads();
+  for (int w = kCombG / 2; w > 0; w >>= 1) {
+    if (g < w) {
+      s_c[g][0][q] += s_c[g + w][0][q];
+      s_c[g][1][q] += s_c[g + w][1][q];
+    }
+    __syncthreads();
+  }
+  if (g == 0) {
+    C = s_c[0][0][q];
+    S = s_c[0][1][q];
+    double phi = 0.0, sk = -1.0;
+    int64_t kc = INT64_MAX;
+    if (i < M) {
+      const int64_t k = k_of_slot[i];
+      kc = canon_of_lex[k];
+      if (nk_out) {
+        nk_out[kc] = C;
+        nk_out[M + kc] = 0.0;
+        nk_out[2 * M + kc] = S;
+        nk_out[3 * M + kc] = 0.0;
+      }
+      const double w = v ? v[kc] + v[M + kc] : 1.0;
+      csw[k] = w * C;
+      csw[M + k] = w * S;
+      const double mag = __builtin_fma(C, C, S * S);
+      phi = w * mag;
+      sk = mag / (double)N;
+    }
+    s_ph[q] = phi;
+    s_mh[q] = sk;
+    s_mk[q] = kc;
+  }
+  __syncthreads();
+  for (int w = kCombK / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      s_ph[tid] += s_ph[tid + w];
+      if (s_mh[tid + w] > s_mh[tid] || (s_mh[tid + w] == s_mh[tid] && s_mk[tid + w] < s_mk[tid])) {
+        s_mh[tid] = s_mh[tid + w];
+        s_mk[tid] = s_mk[tid + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double* b = blk + (int64_t)blockIdx.x * 5;
+    b[0] = s_ph[0];
+    b[1] = 0.0;
+    b[2] = s_mh[0];
+    b[3] = 0.0;
+    b[4] = (double)s_mk[0];
+  }
+}
+
+// table entry (high words) of particle j from the global table
+__device__ __forceinline__ c64 tab64_entry(const double* __restrict__ tab, int64_t N, int R1, int a, int m, int64_t j) {
+  const int mm = m < 0 ? -m : m;
+  const double* e = tab + ((int64_t)(a * R1 + mm) * 4) * N + j;
+  return c64{e[0], m < 0 ? -e[2 * N] : e[2 * N]};
+}
+
+// gradient partials in FP64: gpart[(q * D + a) * N + j]
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_grad64(const Span* __restrict__ runs,
+                                                     const int32_t* __restrict__ chunk_begin,
+                                                     const double* __restrict__ tab, const double* __restrict__ csw,
+                                                     int64_t N, int R1, int64_t M, double* __restrict__ gpart,
+                                                     const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  __shared__ double s_g[kWaves][D][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t jj = j < N ? j : N - 1;
+  const int q = blockIdx.y;
+  const int r0 = chunk_begin[kWaves * q + wave], r1 = chunk_begin[kWaves * q + wave + 1];
+  const c64 z = tab64_entry(tab, N, R1, D - 1, 1, jj);
+  double g[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) g[a] = 0.0;
+  for (int r = r0; r < r1; ++r) {
+    const Span run = runs[r];
+    c64 w = tab64_entry(tab, N, R1, D - 1, run.n[D - 1], jj);
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) w = cmul64(w, tab64_entry(tab, N, R1, a, run.n[a], jj));
+    double q0 = 0.0, qd = 0.0;
+    double nd = (double)run.n[D - 1];
+    const double* cp = csw + run.k0;
+    for (int t = 0; t < run.len; ++t) {
+      const double qs = __builtin_fma(cp[M + t], w.re, -(cp[t] * w.im));  // v (S c - C s)
+      q0 += qs;
+      qd = __builtin_fma(nd, qs, qd);
+      nd += 1.0;
+      w = cmul64(w, z);
+    }
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) g[a] = __builtin_fma((double)run.n[a], q0, g[a]);
+    g[D - 1] += qd;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) s_g[wave][a][lane] = g[a];
+  __syncthreads();
+  if (wave == 0 && j < N) {  // ((w0 + w2) + (w1 + w3))
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      gpart[((int64_t)q * D + a) * N + j] =
+          (s_g[0][a][lane] + s_g[2][a][lane]) + (s_g[1][a][lane] + s_g[3][a][lane]);
+  }
+}
+
+// sum the Q FP64 partials in order, scale by 4 pi / L (and by L with times_L),
+// store in the dd layout with zero low words
+__global__ void __launch_bounds__(kThreads) k_grad_combine64(const double* __restrict__ gpart, int Q, int d,
+                                                             int64_t N, double L, int times_L,
+                                                             double* __restrict__ grad,
+                                                             const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t DN = (int64_t)d * N;
+  if (i >= DN) return;
+  double g = 0.0;
+  for (int q = 0; q < Q; ++q) g += gpart[(int64_t)q * DN + i];
+  const dd tp = two_pi_dd();
+  g *= 2.0 * tp.h / L;
+  if (times_L) g *= L;
+  grad[i] = g;
+  grad[DN + i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+template <int D, int PT>
+static void launch_nk64_t(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units, int64_t nunits,
+                          const double* tab, double* part, const SlotOffsets& so, hipStream_t st, const int* active) {
+  const size_t lds = (size_t)PT * D * c.R1 * 2 * sizeof(double);
+  hipLaunchKernelGGL((k_nk64<D, PT>), dim3((unsigned)nunits), dim3(kThreads), lds, st, segs, nseg, units, tab, c.N,
+                     c.R1, part, c.M, so, active);
+}
+
+template <int D>
+static void launch_nk64_d(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units, int64_t nunits,
+                          const double* tab, double* part, const SlotOffsets& so, hipStream_t st, const int* active) {
+  switch (c.pt) {
+    case 16: launch_nk64_t<D, 16>(c, segs, nseg, units, nunits, tab, part, so, st, active); break;
+    case 4: launch_nk64_t<D, 4>(c, segs, nseg, units, nunits, tab, part, so, st, active); break;
+    default: launch_nk64_t<D, 1>(c, segs, nseg, units, nunits, tab, part, so, st, active); break;
+  }
+}
+
+hipError_t launch_nk64(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units, int64_t nunits,
+                       const double* tab, double* part, const SlotOffsets& so, hipStream_t st, const int* active) {
+  switch (c.d) {
+    case 1: launch_nk64_d<1>(c, segs, nseg, units, nunits, tab, part, so, st, active); break;
+    case 2: launch_nk64_d<2>(c, segs, nseg, units, nunits, tab, part, so, st, active); break;
+    case 3: launch_nk64_d<3>(c, segs, nseg, units, nunits, tab, part, so, st, active); break;
+    default: launch_nk64_d<4>(c, segs, nseg, units, nunits, tab, part, so, st, active); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_nk_combine64(const LaunchCfg& c, const double* part, const int32_t* rows_of,
+                               const int32_t* k_of_slot, const int32_t* canon_of_lex, const double* v,
+                               double* nk_out, double* csw, double* blk, hipStream_t st, const int* active) {
+  hipLaunchKernelGGL(k_nk_combine64, dim3((unsigned)c.combine_blocks), dim3(kThreads), 0, st, part, rows_of,
+                     k_of_slot, c.M, c.N, canon_of_lex, v, nk_out, csw, blk, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad64(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
+                         const double* csw, double* gpart, hipStream_t st, const int* active) {
+  const dim3 grid((unsigned)((c.N + 63) / 64), (unsigned)c.Q);
+  switch (c.d) {
+    case 1: hipLaunchKernelGGL((k_grad64<1>), grid, dim3(kThreads), 0, st, runs, chunk_begin, tab, csw, c.N, c.R1, c.M, gpart, active); break;
+    case 2: hipLaunchKernelGGL((k_grad64<2>), grid, dim3(kThreads), 0, st, runs, chunk_begin, tab, csw, c.N, c.R1, c.M, gpart, active); break;
+    case 3: hipLaunchKernelGGL((k_grad64<3>), grid, dim3(kThreads), 0, st, runs, chunk_begin, tab, csw, c.N, c.R1, c.M, gpart, active); break;
+    default: hipLaunchKernelGGL((k_grad64<4>), grid, dim3(kThreads), 0, st, runs, chunk_begin, tab, csw, c.N, c.R1, c.M, gpart, active); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_combine64(const LaunchCfg& c, const double* gpart, double L, bool times_L, double* grad,
+                                 hipStream_t st, const int* active) {
+  const int64_t DN = (int64_t)c.d * c.N;
+  hipLaunchKernelGGL(k_grad_combine64, dim3((unsigned)((DN + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                     gpart, c.Q, c.d, c.N, L, times_L ? 1 : 0, grad, active);
+  return hipGetLastError();
+}
+
+}  // namespace ss

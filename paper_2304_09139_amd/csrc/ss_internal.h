@@ -28,6 +28,17 @@ struct NkUnit {
   int32_t j0, j1;
 };
 
+constexpr int kSegLen = 8;        // wavevectors per lane in the n(k) pass
+
+// Slot order of the n(k) partials: pieces are sorted by length (longest first),
+// so the pieces longer than t are a prefix 0 .. cnt_t - 1 of the piece list;
+// wavevector t of piece s (t < len_s) is slot off[t] + s, off[t] = sum_{t' < t}
+// cnt_t'.  The M slots are a permutation of the wavevectors in which the lanes
+// of the n(k) pass write consecutive addresses for every t.
+struct SlotOffsets {
+  int32_t off[kSegLen];
+};
+
 // Everything that depends only on (d, R2): the half set in lexicographic (walk)
 // order and in canonical order, the map between them, the runs along the last
 // axis (gradient pass) and the run pieces of length <= kSegLen (n(k) pass).
@@ -44,13 +55,25 @@ struct Plan {
   std::vector<int64_t> run_len_prefix;           // host, nruns+1
   std::vector<int> block_maxlen;                 // host, longest piece of each piece block
   std::vector<Span> seg_host;                    // host copy of the pieces
+  SlotOffsets slot_off{};                        // slot order of the n(k) partials
+  int32_t* k_of_slot = nullptr;                  // device [M]: walk position of each slot
   std::map<int, int32_t*> chunk_begin;           // chunks -> device [chunks+1] run boundaries
   struct NkSched {
     NkUnit* units = nullptr;   // device
-    int32_t* rows_of = nullptr;  // device [M]: partial rows per wavevector
+    int32_t* rows_of = nullptr;  // device [M]: partial rows per slot
     int64_t nunits = 0, rows = 0;
   };
-  std::map<int64_t, NkSched> nk_sched;           // N -> n(k) pass schedule
+  std::map<int64_t, NkSched> nk_sched;           // N -> n(k) pass schedule (single launches)
+  std::map<std::pair<int64_t, int64_t>, NkSched> nk_fixed;  // (N, chunk) -> fixed-chunk schedule (batches)
+};
+
+// Tile shape of the batched launches for one configuration: particles per n(k)
+// unit and wavevectors per gradient block.  A function of (d, N, M) only (looked
+// up in the context's tile table), so that a configuration's reduction order,
+// and hence its results, are the same in every batch.
+struct TileSpec {
+  int64_t nk_chunk;
+  int64_t grad_k;
 };
 
 struct LaunchCfg {
@@ -66,26 +89,52 @@ struct LaunchCfg {
   size_t off_tab, off_part, off_csw, off_gpart, off_blk, off_scalar, total;
 };
 
-constexpr int kSegLen = 8;        // wavevectors per lane in the n(k) pass
 constexpr int kThreads = 256;     // threads per block
 constexpr int kWaves = 4;         // waves per block
 constexpr int kNkPieces = 256;    // run pieces per n(k) block (one per lane)
 constexpr int kTabRun = 8;        // phase-table exponents per thread (one sin/cos pair each)
 constexpr int kCombK = 32;        // wavevectors per block of the partial combine
+constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)
+constexpr int64_t kDefaultGradK = 1024;
 
 }  // namespace ss
 
 namespace ss {
 // optional per-kernel timing: hipEvent pairs recorded on the launch stream
 struct ProfileLog {
+  struct Rec {
+    hipEvent_t a, b;
+    double work;  // pairs (n(k) and gradient passes) or table entries covered by the launch
+  };
   int mask = 0;  // bit k: time kernel k
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];  // 0 n(k) pass, 1 gradient pass, 2 phase table
+  std::vector<Rec> ev[3];  // 0 n(k) pass, 1 gradient pass, 2 phase table
   std::vector<hipEvent_t> pool;
 };
 }  // namespace ss
 
+struct ss_ctx;
+namespace ss {
+// event pair around one launch of kernel `which` when its timing is enabled
+hipEvent_t prof_begin(ss_ctx* ctx, int which, hipStream_t st);
+void prof_end(ss_ctx* ctx, int which, hipStream_t st, hipEvent_t a, double work);
+template <class F>
+hipError_t timed(ss_ctx* ctx, int which, hipStream_t st, double work, F launch) {
+  hipEvent_t a = prof_begin(ctx, which, st);
+  hipError_t e = launch();
+  if (a) prof_end(ctx, which, st, a, work);
+  return e;
+}
+}  // namespace ss
+
+struct ss_tile_entry {
+  int d;            // 0 matches every d
+  int64_t max_N, max_M;
+  ss::TileSpec t;
+};
+
 struct ss_ctx {
   int device = 0;
+  std::vector<ss_tile_entry> tiles;  // batched tile table, first match wins
   std::string last_error;
   std::mutex mu;
   std::map<std::pair<int, int64_t>, ss::Plan*> plans;

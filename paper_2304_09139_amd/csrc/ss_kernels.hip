@@ -28,6 +28,7 @@
 
 #include "ss_dd.h"
 #include "ss_internal.h"
+#include "ss_min.h"
 #include "ss_reduce.h"
 
 namespace ss {
@@ -36,13 +37,10 @@ namespace ss {
 // table of z^m = exp(2 pi i m u) per particle and axis
 // layout: tab[((a * R1 + m) * 4 + c) * N + j], c = (re.hi, re.lo, im.hi, im.lo)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_table(const double* __restrict__ pos, int d, int64_t N, int R1,
-                                                    double* __restrict__ tab,
-    const int* __restrict__ active) {
-  if (active && *active == 0) return;
+__device__ __forceinline__ void table_body(const double* __restrict__ pos, int d, int64_t N, int R1,
+                                           double* __restrict__ tab, int64_t idx) {
   // thread (a, group of kTabRun exponents m0 .. m0 + kTabRun - 1, particle j):
   // z^m0 and z by the exact reduction and the dd sin/cos, then z^m = z^(m-1) z
-  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int groups = (R1 + kTabRun - 1) / kTabRun;
   const int64_t total = (int64_t)d * groups * N;
   if (idx >= total) return;
@@ -67,6 +65,12 @@ __global__ void __launch_bounds__(kThreads) k_table(const double* __restrict__ p
   }
 }
 
+__global__ void __launch_bounds__(kThreads) k_table(const double* __restrict__ pos, int d, int64_t N, int R1,
+                                                    double* __restrict__ tab, const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  table_body(pos, d, N, R1, tab, (int64_t)blockIdx.x * kThreads + threadIdx.x);
+}
+
 // entry z_a^m of the particle table staged in LDS ([a][m][c] per particle),
 // conjugated for negative exponents (z^-m = conj z^m for |z| = 1)
 __device__ __forceinline__ cdd lds_entry(const double* tp, int R1, int a, int m) {
@@ -85,14 +89,11 @@ __device__ __forceinline__ cdd lds_entry(const double* tp, int R1, int a, int m)
 // part[((row * 4) + c) * M + k], c = (C.hi, C.lo, S.hi, S.lo), k in walk order.
 // ---------------------------------------------------------------------------
 template <int D, int PT>
-__global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, int64_t nseg,
-                                                 const NkUnit* __restrict__ units, const double* __restrict__ tab,
-                                                 int64_t N, int R1, double* __restrict__ part, int64_t M,
-    const int* __restrict__ active) {
-  if (active && *active == 0) return;
-  extern __shared__ double lds[];  // [PT][D][R1][4]
+__device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t nseg, const NkUnit u,
+                                        const double* __restrict__ tab, int64_t N, int R1,
+                                        double* __restrict__ part, int64_t M, const SlotOffsets& so,
+                                        double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  const NkUnit u = units[blockIdx.x];
   const int64_t s = (int64_t)u.block * kNkPieces + tid;
   const Span sg = segs[s < nseg ? s : nseg - 1];
   const int len = s < nseg ? sg.len : 0;
@@ -136,39 +137,50 @@ __global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, 
       }
     }
   }
+  // slot order: for each t the lanes of a wave write consecutive slots
   double* out = part + (int64_t)u.row * 4 * M;
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) {
     if (t < len) {
-      const int64_t k = sg.k0 + t;
-      out[k] = crh[t];
-      out[M + k] = crl[t];
-      out[2 * M + k] = cih[t];
-      out[3 * M + k] = cil[t];
+      const int64_t slot = so.off[t] + s;
+      out[slot] = crh[t];
+      out[M + slot] = crl[t];
+      out[2 * M + slot] = cih[t];
+      out[3 * M + slot] = cil[t];
     }
   }
+}
+
+template <int D, int PT>
+__global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, int64_t nseg,
+                                                 const NkUnit* __restrict__ units, const double* __restrict__ tab,
+                                                 int64_t N, int R1, double* __restrict__ part, int64_t M,
+                                                 const SlotOffsets so, const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  extern __shared__ double lds[];  // [PT][D][R1][4]
+  nk_body<D, PT>(segs, nseg, units[blockIdx.x], tab, N, R1, part, M, so, lds);
 }
 
 // ---------------------------------------------------------------------------
 // combine the P chunk partials per wavevector (fixed order, accurate dd sums);
 // write n~ in canonical order, (v C, v S) in walk order, and per-block Phi and
-// S_max partials.  blk[b * 5 + (0..4)] = Phi.hi, Phi.lo, Smax.hi, Smax.lo, kmax
+// S_max partials.  Block b covers slots b kCombK .. (b + 1) kCombK - 1 (reads of
+// consecutive slots are contiguous).  blk[b * 5 + (0..4)] = Phi.hi, Phi.lo,
+// Smax.hi, Smax.lo, canonical index of the maximum
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restrict__ part,
-                                                         const int32_t* __restrict__ rows_of, int64_t M,
-                                                         int64_t N, const int32_t* __restrict__ canon_of_lex,
-                                                         const double* __restrict__ v, double* __restrict__ nk_out,
-                                                         double* __restrict__ csw, double* __restrict__ blk,
-    const int* __restrict__ active) {
-  if (active && *active == 0) return;
-  // thread (q, g): wavevector i = block * kCombK + q; partial group g sums rows
+__device__ __forceinline__ void combine_body(const double* __restrict__ part, const int32_t* __restrict__ rows_of,
+                                             const int32_t* __restrict__ k_of_slot, int64_t M, int64_t N,
+                                             const int32_t* __restrict__ canon_of_lex, const double* __restrict__ v,
+                                             double* __restrict__ nk_out, double* __restrict__ csw,
+                                             double* __restrict__ blk, int64_t bidx) {
+  // thread (q, g): slot i = bidx * kCombK + q; partial group g sums rows
   // g, g + kCombG, ...; the groups are then added pairwise in a fixed tree
   constexpr int kCombG = kThreads / kCombK;
   __shared__ double s_c[kCombG][4][kCombK];
   __shared__ double s_ph[kCombK], s_pl[kCombK], s_mh[kCombK], s_ml[kCombK];
   __shared__ int64_t s_mk[kCombK];
   const int tid = threadIdx.x, q = tid % kCombK, g = tid / kCombK;
-  const int64_t i = (int64_t)blockIdx.x * kCombK + q;
+  const int64_t i = bidx * kCombK + q;
   dd C{0.0, 0.0}, S{0.0, 0.0};
   if (i < M) {
     const int64_t P = rows_of[i];
@@ -200,7 +212,8 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restric
     dd phi{0.0, 0.0}, sk{-1.0, 0.0};
     int64_t kc = INT64_MAX;
     if (i < M) {
-      kc = canon_of_lex[i];
+      const int64_t k = k_of_slot[i];
+      kc = canon_of_lex[k];
       if (nk_out) {
         nk_out[kc] = C.h;
         nk_out[M + kc] = C.l;
@@ -210,10 +223,10 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restric
       const dd w = v ? dd{v[kc], v[M + kc]} : dd{1.0, 0.0};
       const dd Cw = v ? dd_mul(w, C) : C;
       const dd Sw = v ? dd_mul(w, S) : S;
-      csw[i] = Cw.h;
-      csw[M + i] = Cw.l;
-      csw[2 * M + i] = Sw.h;
-      csw[3 * M + i] = Sw.l;
+      csw[k] = Cw.h;
+      csw[M + k] = Cw.l;
+      csw[2 * M + k] = Sw.h;
+      csw[3 * M + k] = Sw.l;
       const dd mag = dd_add(dd_mul(C, C), dd_mul(S, S));
       phi = v ? dd_mul(w, mag) : mag;
       sk = dd_div_d(mag, (double)N);
@@ -240,13 +253,24 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restric
     __syncthreads();
   }
   if (tid == 0) {
-    double* b = blk + (int64_t)blockIdx.x * 5;
+    double* b = blk + bidx * 5;
     b[0] = s_ph[0];
     b[1] = s_pl[0];
     b[2] = s_mh[0];
     b[3] = s_ml[0];
     b[4] = (double)s_mk[0];
   }
+}
+
+__global__ void __launch_bounds__(kThreads) k_nk_combine(const double* __restrict__ part,
+                                                         const int32_t* __restrict__ rows_of,
+                                                         const int32_t* __restrict__ k_of_slot, int64_t M,
+                                                         int64_t N, const int32_t* __restrict__ canon_of_lex,
+                                                         const double* __restrict__ v, double* __restrict__ nk_out,
+                                                         double* __restrict__ csw, double* __restrict__ blk,
+                                                         const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  combine_body(part, rows_of, k_of_slot, M, N, canon_of_lex, v, nk_out, csw, blk, blockIdx.x);
 }
 
 // single block: fixed-order reduction of the per-block partials
@@ -280,17 +304,14 @@ __device__ __forceinline__ cdd tab_entry(const double* __restrict__ tab, int64_t
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs,
-                                                   const int32_t* __restrict__ chunk_begin,
-                                                   const double* __restrict__ tab, const double* __restrict__ csw,
-                                                   int64_t N, int R1, int64_t M, double* __restrict__ gpart,
-    const int* __restrict__ active) {
-  if (active && *active == 0) return;
+__device__ __forceinline__ void grad_body(const Span* __restrict__ runs, const int32_t* __restrict__ chunk_begin,
+                                          const double* __restrict__ tab, const double* __restrict__ csw,
+                                          int64_t N, int R1, int64_t M, double* __restrict__ gpart, int64_t pblock,
+                                          int q) {
   __shared__ double s_g[kWaves][2 * D][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t j = pblock * 64 + lane;
   const int64_t jj = j < N ? j : N - 1;
-  const int q = blockIdx.y;
   const int r0 = chunk_begin[kWaves * q + wave], r1 = chunk_begin[kWaves * q + wave + 1];
   const cdd z = tab_entry(tab, N, R1, D - 1, 1, jj);
   double gh[D], gl[D];
@@ -351,13 +372,22 @@ __global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs
   }
 }
 
-// sum the Q gradient partials (fixed order) and scale by 4 pi / L:
-// dPhi/dr_{j,a} = (4 pi / L) sum_k v_k n_{k,a} (S_k c_jk - C_k s_jk)
-__global__ void __launch_bounds__(kThreads) k_grad_combine(const double* __restrict__ gpart, int Q, int d, int64_t N,
-                                                           double L, double* __restrict__ grad,
-    const int* __restrict__ active) {
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs,
+                                                   const int32_t* __restrict__ chunk_begin,
+                                                   const double* __restrict__ tab, const double* __restrict__ csw,
+                                                   int64_t N, int R1, int64_t M, double* __restrict__ gpart,
+                                                   const int* __restrict__ active) {
   if (active && *active == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // a * N + j
+  grad_body<D>(runs, chunk_begin, tab, csw, N, R1, M, gpart, blockIdx.x, blockIdx.y);
+}
+
+// sum the Q gradient partials (fixed order) and scale by 4 pi / L:
+// dPhi/dr_{j,a} = (4 pi / L) sum_k v_k n_{k,a} (S_k c_jk - C_k s_jk); with
+// times_L the result is then multiplied by L (the gradient with respect to the
+// fractional coordinates, as the minimiser uses it)
+__device__ __forceinline__ void gcomb_body(const double* __restrict__ gpart, int Q, int d, int64_t N, double L,
+                                           bool times_L, double* __restrict__ grad, int64_t i) {
   const int64_t DN = (int64_t)d * N;
   if (i >= DN) return;
   dd g{0.0, 0.0};
@@ -365,8 +395,83 @@ __global__ void __launch_bounds__(kThreads) k_grad_combine(const double* __restr
   const dd tp = two_pi_dd();
   const dd scale = dd_div_d(dd{2.0 * tp.h, 2.0 * tp.l}, L);
   g = dd_mul(g, scale);
+  if (times_L) g = dd_mul_d(g, L);
   grad[i] = g.h;
   grad[DN + i] = g.l;
+}
+
+__global__ void __launch_bounds__(kThreads) k_grad_combine(const double* __restrict__ gpart, int Q, int d, int64_t N,
+                                                           double L, double* __restrict__ grad,
+                                                           const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  gcomb_body(gpart, Q, d, N, L, false, grad, (int64_t)blockIdx.x * kThreads + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// batched launches: one grid covers the blocks of many configurations; block
+// b runs block units[b].idx of configuration units[b].slot's own grid, with the
+// same arithmetic and order as the single-configuration kernels, so a
+// configuration's results do not depend on what else is in the batch.  With
+// gate != 0 the blocks of a configuration whose quench has stopped exit at once.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) kb_table(const EvalSlot* __restrict__ es,
+                                                     const BUnit* __restrict__ units, int which, int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  table_body(E.pos[which], E.d, E.N, E.R1, E.tab, (int64_t)u.idx * kThreads + threadIdx.x);
+}
+
+template <int D, int PT>
+__global__ void __launch_bounds__(kThreads) kb_nk(const EvalSlot* __restrict__ es, const BUnit* __restrict__ units,
+                                                  int gate) {
+  extern __shared__ double lds[];  // [PT][D][R1][4], sized for the largest R1 of the launch
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  nk_body<D, PT>(E.segs, E.nsegs, E.units[u.idx], E.tab, E.N, E.R1, E.part, E.M, E.so, lds);
+}
+
+__global__ void __launch_bounds__(kThreads) kb_combine(const EvalSlot* __restrict__ es,
+                                                       const BUnit* __restrict__ units, int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  combine_body(E.part, E.rows_of, E.k_of_slot, E.M, E.N, E.canon_of_lex, E.v, nullptr, E.csw, E.blk, u.idx);
+}
+
+// one block per listed configuration: Phi and S_max of the iterate
+__global__ void __launch_bounds__(kThreads) kb_final(const EvalSlot* __restrict__ es,
+                                                     const int32_t* __restrict__ list) {
+  const EvalSlot& E = es[list[blockIdx.x]];
+  dd phi, sm;
+  double kk;
+  reduce_energy_partials(E.blk, E.combine_blocks, &phi, &sm, &kk);
+  if (threadIdx.x == 0) {
+    E.phi[0] = phi.h;
+    E.phi[1] = phi.l;
+    E.smax[0] = sm.h;
+    E.smax[1] = sm.l;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) kb_grad(const EvalSlot* __restrict__ es, const BUnit* __restrict__ units,
+                                                    int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  const int64_t pblock = u.idx % E.pblocks;
+  const int q = (int)(u.idx / E.pblocks);
+  grad_body<D>(E.runs, E.chunk_begin, E.tab, E.csw, E.N, E.R1, E.M, E.gpart, pblock, q);
+}
+
+__global__ void __launch_bounds__(kThreads) kb_gcomb(const EvalSlot* __restrict__ es,
+                                                     const BUnit* __restrict__ units, int which, int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  gcomb_body(E.gpart, E.Q, E.d, E.N, E.L, E.L != 1.0, E.grad[which], (int64_t)u.idx * kThreads + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -517,39 +622,46 @@ hipError_t launch_table(const double* pos, int d, int64_t N, int R1, double* tab
 
 template <int D, int PT>
 static hipError_t launch_nk_t(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units,
-                              int64_t nunits, const double* tab, double* part, hipStream_t st, const int* active) {
+                              int64_t nunits, const double* tab, double* part, const SlotOffsets& so, hipStream_t st,
+                              const int* active) {
   const size_t lds = (size_t)PT * D * c.R1 * 4 * sizeof(double);
   hipLaunchKernelGGL((k_nk<D, PT>), dim3((unsigned)nunits), dim3(kThreads), lds, st, segs, nseg, units, tab, c.N,
-                     c.R1, part, c.M, active);
+                     c.R1, part, c.M, so, active);
   return hipGetLastError();
 }
 
 template <int D>
 static hipError_t launch_nk_d(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units,
-                              int64_t nunits, const double* tab, double* part, hipStream_t st, const int* active) {
+                              int64_t nunits, const double* tab, double* part, const SlotOffsets& so, hipStream_t st,
+                              const int* active) {
   switch (c.pt) {
-    case 16: return launch_nk_t<D, 16>(c, segs, nseg, units, nunits, tab, part, st, active);
-    case 4: return launch_nk_t<D, 4>(c, segs, nseg, units, nunits, tab, part, st, active);
-    default: return launch_nk_t<D, 1>(c, segs, nseg, units, nunits, tab, part, st, active);
+    case 16: return launch_nk_t<D, 16>(c, segs, nseg, units, nunits, tab, part, so, st, active);
+    case 4: return launch_nk_t<D, 4>(c, segs, nseg, units, nunits, tab, part, so, st, active);
+    default: return launch_nk_t<D, 1>(c, segs, nseg, units, nunits, tab, part, so, st, active);
   }
 }
 
 hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const NkUnit* units, int64_t nunits,
-                     const double* tab, double* part, hipStream_t st, const int* active) {
+                     const double* tab, double* part, const SlotOffsets& so, hipStream_t st, const int* active) {
   switch (c.d) {
-    case 1: return launch_nk_d<1>(c, segs, nseg, units, nunits, tab, part, st, active);
-    case 2: return launch_nk_d<2>(c, segs, nseg, units, nunits, tab, part, st, active);
-    case 3: return launch_nk_d<3>(c, segs, nseg, units, nunits, tab, part, st, active);
-    default: return launch_nk_d<4>(c, segs, nseg, units, nunits, tab, part, st, active);
+    case 1: return launch_nk_d<1>(c, segs, nseg, units, nunits, tab, part, so, st, active);
+    case 2: return launch_nk_d<2>(c, segs, nseg, units, nunits, tab, part, so, st, active);
+    case 3: return launch_nk_d<3>(c, segs, nseg, units, nunits, tab, part, so, st, active);
+    default: return launch_nk_d<4>(c, segs, nseg, units, nunits, tab, part, so, st, active);
   }
 }
 
 hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* rows_of,
-                             const int32_t* canon_of_lex, const double* v, double* nk_out, double* csw, double* blk,
-                             double* phi, double* smax, double* kmax, hipStream_t st, const int* active) {
-  hipLaunchKernelGGL(k_nk_combine, dim3((unsigned)c.combine_blocks), dim3(kThreads), 0, st, part, rows_of, c.M, c.N,
-                     canon_of_lex, v, nk_out, csw, blk, active);
-  if (phi) hipLaunchKernelGGL(k_final, dim3(1), dim3(kThreads), 0, st, blk, c.combine_blocks, phi, smax, kmax, active);
+                             const int32_t* k_of_slot, const int32_t* canon_of_lex, const double* v, double* nk_out,
+                             double* csw, double* blk, hipStream_t st, const int* active) {
+  hipLaunchKernelGGL(k_nk_combine, dim3((unsigned)c.combine_blocks), dim3(kThreads), 0, st, part, rows_of, k_of_slot,
+                     c.M, c.N, canon_of_lex, v, nk_out, csw, blk, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_final(const LaunchCfg& c, const double* blk, double* phi, double* smax, double* kmax, hipStream_t st,
+                        const int* active) {
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kThreads), 0, st, blk, c.combine_blocks, phi, smax, kmax, active);
   return hipGetLastError();
 }
 
@@ -577,6 +689,63 @@ hipError_t launch_grad_combine(const LaunchCfg& c, const double* gpart, double L
   const int64_t DN = (int64_t)c.d * c.N;
   hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((DN + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, gpart,
                      c.Q, c.d, c.N, L, grad, active);
+  return hipGetLastError();
+}
+
+// batched launch helpers (n = number of units; nothing is launched for n = 0)
+hipError_t launch_batch_table(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
+                              hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_table, dim3((unsigned)n), dim3(kThreads), 0, st, es, units, which, gate);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_batch_nk_d(int pt, int R1max, const EvalSlot* es, const BUnit* units, int64_t n, int gate,
+                                    hipStream_t st) {
+  const size_t lds = (size_t)pt * D * R1max * 4 * sizeof(double);
+  switch (pt) {
+    case 16: hipLaunchKernelGGL((kb_nk<D, 16>), dim3((unsigned)n), dim3(kThreads), lds, st, es, units, gate); break;
+    case 4: hipLaunchKernelGGL((kb_nk<D, 4>), dim3((unsigned)n), dim3(kThreads), lds, st, es, units, gate); break;
+    default: hipLaunchKernelGGL((kb_nk<D, 1>), dim3((unsigned)n), dim3(kThreads), lds, st, es, units, gate); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_nk(int d, int pt, int R1max, const EvalSlot* es, const BUnit* units, int64_t n, int gate,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  switch (d) {
+    case 1: return launch_batch_nk_d<1>(pt, R1max, es, units, n, gate, st);
+    case 2: return launch_batch_nk_d<2>(pt, R1max, es, units, n, gate, st);
+    case 3: return launch_batch_nk_d<3>(pt, R1max, es, units, n, gate, st);
+    default: return launch_batch_nk_d<4>(pt, R1max, es, units, n, gate, st);
+  }
+}
+
+hipError_t launch_batch_combine(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_combine, dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_final(const EvalSlot* es, const int32_t* list, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_final, dim3((unsigned)n), dim3(kThreads), 0, st, es, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_grad(int d, const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  switch (d) {
+    case 1: hipLaunchKernelGGL((kb_grad<1>), dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate); break;
+    case 2: hipLaunchKernelGGL((kb_grad<2>), dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate); break;
+    case 3: hipLaunchKernelGGL((kb_grad<3>), dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate); break;
+    default: hipLaunchKernelGGL((kb_grad<4>), dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gcomb(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
+                              hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_gcomb, dim3((unsigned)n), dim3(kThreads), 0, st, es, units, which, gate);
   return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@
 #include "ss.h"
 #include "ss_dd.h"
 #include "ss_internal.h"
+#include "ss_min.h"
 #include "ss_reduce.h"
 
 namespace ss {
@@ -43,52 +44,7 @@ namespace ss {
 int prepare(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg);
 int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg& c, const double* v_dev,
                      const double* pos, double* phi, double* smax, double* grad, double* nk, char* ws,
-                     hipStream_t st, double* kmax, const int* active);
-
-constexpr int kMaxHistory = 16;
-constexpr int kMaxWindow = 256;
-constexpr int kDotBlocks = 120;
-constexpr int kMaxDots = 2 + 2 * kMaxHistory;  // 34
-constexpr int kMaxComb = 1 + 2 * kMaxHistory;  // 33
-
-// control state of one quench (device memory)
-struct MinState {
-  int32_t running;    // 1 while the quench continues; every kernel of a tick reads it
-  int32_t status;     // 0 converged, 1 stalled, 2 iteration cap, 3 non-finite (valid once running == 0)
-  int32_t phase;      // 0: a new direction is needed; 1: a trial step is pending
-  int32_t new_dir;    // 1 when this tick computed a new direction
-  int32_t accepted;   // 1 when this tick accepted its trial
-  int32_t halvings, ls_fail, k, spare;
-  int32_t slot[kMaxHistory];  // history slots, oldest first
-  int32_t ncoef;
-  int32_t coef_vec[kMaxComb];  // 0: g, 1 + s: S[s], kMaxHistory + 2 + s: Y[s]
-  int64_t iter, evals;
-  double alpha;
-  double f[2], smax[2], ft[2], smaxt[2], gp[2];
-  double coef[kMaxComb][2];
-  double SY[kMaxHistory][kMaxHistory][2];  // s_i . y_j for i <= j (upper triangle R)
-  double YY[kMaxHistory][kMaxHistory][2];
-  double dir_dots[kMaxDots][2];    // s_i.g (k), y_i.g (k), g.g, max|g|
-  double trial_dots[kMaxDots][2];  // s.y, y.y, s_i.y (k), y.y_i (k) of the fresh pair
-  double fhist[2 * kMaxWindow][2];
-};
-
-struct MinParams {
-  int32_t m, W, max_halvings, max_ls_fail;
-  int64_t max_iter;
-  double s_floor, stall_ratio, c1, step;  // step = step_cap * N^(-1/d)
-};
-
-// the vectors of one quench
-struct VecSet {
-  double* x;  // positions (the caller's buffer)
-  double* g;
-  double* xt;
-  double* gt;
-  double* p;
-  double* S[kMaxHistory + 1];
-  double* Y[kMaxHistory + 1];
-};
+                     hipStream_t st, double* kmax, const int* active, bool fp64);
 
 __device__ __forceinline__ dd ld(const double* a) { return dd{a[0], a[1]}; }
 __device__ __forceinline__ void st(double* a, dd v) {
@@ -195,7 +151,18 @@ __device__ void direction_logic(MinState& S, const MinParams& P, int i) {
       S.new_dir = 0;
       return;
     }
-    const dd scale = dd_div(dd{P.step, 0.0}, gmax);
+    // at most step_cap of the mean spacing, and at most 2 Phi / g.g: the energy's
+    // minimum is 0, and there the line along -g meets the minimum of the
+    // isotropic quadratic through (Phi, g)
+    dd scale = dd_div(dd{P.step, 0.0}, gmax);
+    const dd polyak = dd_div(dd_mul_d(ld(S.f), 2.0), gg);
+    if (dd_less(polyak, scale)) scale = polyak;
+    if (scale.h == 0.0) {  // Phi = 0: a ground state
+      S.status = 0;
+      S.running = 0;
+      S.new_dir = 0;
+      return;
+    }
     st(S.coef[0], dd_neg(scale));
     S.coef_vec[0] = 0;
     S.ncoef = 1;
@@ -220,7 +187,7 @@ __device__ void direction_logic(MinState& S, const MinParams& P, int i) {
 
 // p <- sum_c coef_c v_c (accurate dd sums in c order) when a new direction was
 // made this tick; then xt <- x + alpha p (alpha a power of two)
-__global__ void __launch_bounds__(kThreads) k_step(VecSet V, const MinState* S_, int64_t nv) {
+__device__ __forceinline__ void step_body(const VecSet& V, const MinState* S_, int64_t nv, int64_t bx) {
   const MinState& S = *S_;
   if (!S.running) return;
   __shared__ double s_ch[kMaxComb], s_cl[kMaxComb];
@@ -233,7 +200,7 @@ __global__ void __launch_bounds__(kThreads) k_step(VecSet V, const MinState* S_,
     s_v[threadIdx.x] = vec_of(V, S.coef_vec[threadIdx.x]);
   }
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = bx * kThreads + threadIdx.x;
   if (i >= nv) return;
   dd p;
   if (nd) {
@@ -249,6 +216,10 @@ __global__ void __launch_bounds__(kThreads) k_step(VecSet V, const MinState* S_,
   const dd r = dd_add(vload(V.x, nv, i), dd{a * p.h, a * p.l});
   V.xt[i] = r.h;
   V.xt[nv + i] = r.l;
+}
+
+__global__ void __launch_bounds__(kThreads) k_step(VecSet V, const MinState* S_, int64_t nv) {
+  step_body(V, S_, nv, blockIdx.x);
 }
 
 // gradient with respect to the fractional coordinates: g <- L * dPhi/dr
@@ -297,13 +268,14 @@ __device__ void top_of_iteration(MinState& S, const MinParams& P, int lane, int6
 }
 
 // after the starting evaluation (f, smax set): finite check and the tests
-__global__ void __launch_bounds__(64) k_init(MinState* S_, MinParams P) {
+// keep != 0: the kept (s, y) pairs survive (a change of evaluation precision)
+__device__ __forceinline__ void init_body(MinState* S_, const MinParams& P, int keep) {
   MinState& S = *S_;
   const int lane = threadIdx.x;
   if (lane == 0) {
     S.iter = 0;
     S.evals = 1;
-    S.k = 0;
+    if (!keep) S.k = 0;
     S.phase = 0;
     S.new_dir = 0;
     S.accepted = 0;
@@ -324,6 +296,8 @@ __global__ void __launch_bounds__(64) k_init(MinState* S_, MinParams P) {
   }
   top_of_iteration(S, P, lane, 0, f, smax);
 }
+
+__global__ void __launch_bounds__(64) k_init(MinState* S_, MinParams P, int keep) { init_body(S_, P, keep); }
 
 // the Armijo test and its consequences (run by the last block of the trial
 // products; all threads call it for the barriers, wave 0 does the work).  Lane 0
@@ -449,19 +423,17 @@ __device__ void decide_logic(MinState& S, const MinParams& P, int i) {
 // pair s = xt - x, y = gt - g (computed on the fly; blocks of product 0 also
 // write it to S[spare], Y[spare]) against the history.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_dots(VecSet V, MinState* S_, int mode, int64_t nv,
-                                                   double* __restrict__ partial) {
+__device__ __forceinline__ void dots_body(const VecSet& V, MinState* S_, int mode, int64_t nv,
+                                          double* __restrict__ partial, int bx, int q, int G) {
   MinState& S = *S_;
   if (!S.running) return;
   if (mode == 0 && S.phase != 0) return;
   __shared__ double s_h[kThreads / 64], s_l[kThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int q = blockIdx.y;
-  const int G = gridDim.x;
   const int k = S.k;
   const int n = 2 * k + 2;
   const int64_t per = (nv + G - 1) / G;
-  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i0 = (int64_t)bx * per;
   const int64_t i1 = i0 + per < nv ? i0 + per : nv;
   const int spare = S.spare;
   if (mode == 1 && q == 0) {
@@ -532,17 +504,22 @@ __global__ void __launch_bounds__(kThreads) k_dots(VecSet V, MinState* S_, int m
       const dd o{s_h[w], s_l[w]};
       r = isdot ? dd_add(r, o) : (dd_less(r, o) ? o : r);
     }
-    partial[((int64_t)q * G + blockIdx.x) * 2] = r.h;
-    partial[((int64_t)q * G + blockIdx.x) * 2 + 1] = r.l;
+    partial[((int64_t)q * G + bx) * 2] = r.h;
+    partial[((int64_t)q * G + bx) * 2 + 1] = r.l;
   }
+}
+
+__global__ void __launch_bounds__(kThreads) k_dots(VecSet V, MinState* S_, int mode, int64_t nv,
+                                                   double* __restrict__ partial) {
+  dots_body(V, S_, mode, nv, partial, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // one block: each product's range partials summed in range order (kSubs
 // sub-ranges in parallel, then the sub-range sums in order), then the
 // direction (mode 0) or the Armijo decision (mode 1)
-__global__ void __launch_bounds__(kThreads) k_dots_final(MinState* S_, MinParams P, int mode, int G,
-                                                         const double* __restrict__ partial,
-                                                         const double* __restrict__ eblk, int64_t neblk) {
+__device__ __forceinline__ void dots_final_body(MinState* S_, const MinParams& P, int mode, int G,
+                                                const double* __restrict__ partial, const double* __restrict__ eblk,
+                                                int64_t neblk) {
   MinState& S = *S_;
   if (!S.running) return;
   if (mode == 0 && S.phase != 0) return;
@@ -594,15 +571,97 @@ __global__ void __launch_bounds__(kThreads) k_dots_final(MinState* S_, MinParams
   else decide_logic(S, P, tid);
 }
 
+__global__ void __launch_bounds__(kThreads) k_dots_final(MinState* S_, MinParams P, int mode, int G,
+                                                         const double* __restrict__ partial,
+                                                         const double* __restrict__ eblk, int64_t neblk) {
+  dots_final_body(S_, P, mode, G, partial, eblk, neblk);
+}
+
 // x <- xt, g <- gt after an accepted trial
-__global__ void __launch_bounds__(kThreads) k_accept(VecSet V, const MinState* S_, int64_t nv) {
+__device__ __forceinline__ void accept_body(const VecSet& V, const MinState* S_, int64_t nv, int64_t bx) {
   if (!S_->accepted) return;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t i = bx * kThreads + threadIdx.x;
   if (i >= nv) return;
   V.x[i] = V.xt[i];
   V.x[nv + i] = V.xt[nv + i];
   V.g[i] = V.gt[i];
   V.g[nv + i] = V.gt[nv + i];
+}
+
+__global__ void __launch_bounds__(kThreads) k_accept(VecSet V, const MinState* S_, int64_t nv) {
+  accept_body(V, S_, nv, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// batched minimiser kernels: the same bodies over many configurations (see the
+// batched energy kernels for the unit convention)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) kb_dots(const MinSlot* __restrict__ ms, const BUnit* __restrict__ units,
+                                                    int mode) {
+  const BUnit u = units[blockIdx.x];
+  const MinSlot& C = ms[u.slot];
+  const int G = C.dot_blocks;
+  dots_body(C.V, C.S, mode, C.nv, C.partial, u.idx % G, u.idx / G, G);
+}
+
+__global__ void __launch_bounds__(kThreads) kb_dots_final(const MinSlot* __restrict__ ms,
+                                                          const int32_t* __restrict__ list, int mode) {
+  const MinSlot& C = ms[list[blockIdx.x]];
+  dots_final_body(C.S, C.P, mode, C.dot_blocks, C.partial, C.eblk, C.neblk);
+}
+
+__global__ void __launch_bounds__(kThreads) kb_step(const MinSlot* __restrict__ ms, const BUnit* __restrict__ units) {
+  const BUnit u = units[blockIdx.x];
+  const MinSlot& C = ms[u.slot];
+  step_body(C.V, C.S, C.nv, u.idx);
+}
+
+__global__ void __launch_bounds__(kThreads) kb_accept(const MinSlot* __restrict__ ms,
+                                                      const BUnit* __restrict__ units) {
+  const BUnit u = units[blockIdx.x];
+  const MinSlot& C = ms[u.slot];
+  accept_body(C.V, C.S, C.nv, u.idx);
+}
+
+__global__ void __launch_bounds__(64) kb_init(const MinSlot* __restrict__ ms, const int32_t* __restrict__ list) {
+  const MinSlot& C = ms[list[blockIdx.x]];
+  init_body(C.S, C.P, 0);
+}
+
+// running word of each listed configuration, gathered for one copy to the host
+__global__ void __launch_bounds__(kThreads) kb_flags(const MinSlot* __restrict__ ms, const int32_t* __restrict__ list,
+                                                     int64_t n, int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int32_t s = list[i];
+  out[s] = ms[s].S->running;
+}
+
+hipError_t launch_batch_dots(const MinSlot* ms, const BUnit* units, int64_t n, int mode, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_dots, dim3((unsigned)n), dim3(kThreads), 0, st, ms, units, mode);
+  return hipGetLastError();
+}
+hipError_t launch_batch_dots_final(const MinSlot* ms, const int32_t* list, int64_t n, int mode, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_dots_final, dim3((unsigned)n), dim3(kThreads), 0, st, ms, list, mode);
+  return hipGetLastError();
+}
+hipError_t launch_batch_step(const MinSlot* ms, const BUnit* units, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_step, dim3((unsigned)n), dim3(kThreads), 0, st, ms, units);
+  return hipGetLastError();
+}
+hipError_t launch_batch_accept(const MinSlot* ms, const BUnit* units, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_accept, dim3((unsigned)n), dim3(kThreads), 0, st, ms, units);
+  return hipGetLastError();
+}
+hipError_t launch_batch_init(const MinSlot* ms, const int32_t* list, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_init, dim3((unsigned)n), dim3(64), 0, st, ms, list);
+  return hipGetLastError();
+}
+hipError_t launch_batch_flags(const MinSlot* ms, const int32_t* list, int64_t n, int32_t* out, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(kb_flags, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, ms, list, n,
+                       out);
+  return hipGetLastError();
 }
 
 namespace {
@@ -644,6 +703,27 @@ void carve(char* base, int64_t nv, double* x, Layout* L) {
 
 size_t minimize_extra_bytes(int64_t nv) { return lbfgs_bytes(nv); }
 
+bool min_opts_valid(const ss_min_opts* op) {
+  return op && op->history >= 1 && op->history <= kMaxHistory && op->max_iter >= 0 && op->stall_window >= 1 &&
+         op->stall_window <= kMaxWindow && op->max_halvings >= 0 && op->max_ls_fail >= 1 && op->step_cap > 0.0 &&
+         op->c1 > 0.0 && op->c1 < 1.0 && op->stall_ratio > 0.0 && op->precision >= 0 && op->precision <= 2 &&
+         op->fp64_floor >= 0.0;
+}
+
+MinParams min_params(const ss_min_opts* op, const ss_problem* prob) {
+  MinParams P;
+  P.m = op->history;
+  P.W = op->stall_window;
+  P.max_halvings = op->max_halvings;
+  P.max_ls_fail = op->max_ls_fail;
+  P.max_iter = op->max_iter;
+  P.s_floor = op->s_floor;
+  P.stall_ratio = op->stall_ratio;
+  P.c1 = op->c1;
+  P.step = op->step_cap * pow((double)prob->N, -1.0 / (double)prob->d);
+  return P;
+}
+
 }  // namespace ss
 
 using namespace ss;
@@ -664,9 +744,7 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
     ctx->last_error = "vkind != 0 needs v_dev";
     return SS_EINVAL;
   }
-  if (op->history < 1 || op->history > kMaxHistory || op->max_iter < 0 || op->stall_window < 1 ||
-      op->stall_window > kMaxWindow || op->max_halvings < 0 || op->max_ls_fail < 1 || !(op->step_cap > 0.0) ||
-      !(op->c1 > 0.0 && op->c1 < 1.0) || !(op->stall_ratio > 0.0)) {
+  if (!min_opts_valid(op)) {
     ctx->last_error = "invalid minimiser options";
     return SS_EINVAL;
   }
@@ -682,16 +760,6 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
   carve(ews + c.total, nv, pos_dev, &Lay);
   VecSet& V = Lay.V;
   MinState* S = Lay.state;
-  MinParams P;
-  P.m = op->history;
-  P.W = op->stall_window;
-  P.max_halvings = op->max_halvings;
-  P.max_ls_fail = op->max_ls_fail;
-  P.max_iter = op->max_iter;
-  P.s_floor = op->s_floor;
-  P.stall_ratio = op->stall_ratio;
-  P.c1 = op->c1;
-  P.step = op->step_cap * pow((double)prob->N, -1.0 / (double)prob->d);
   const int blocks_nv = (int)((nv + kThreads - 1) / kThreads);
   const int dot_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (nv + 1023) / 1024));
   const double L = prob->L;
@@ -704,8 +772,9 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
     return err == SS_OK;
   };
   const int* running = &S->running;
+  bool fp64 = false;
   auto eval = [&](const double* x, double* phi, double* smax, double* g, const int* active) -> bool {
-    int e = energy_grad_impl(ctx, prob, pl, c, v_dev, x, phi, smax, g, nullptr, ews, st, nullptr, active);
+    int e = energy_grad_impl(ctx, prob, pl, c, v_dev, x, phi, smax, g, nullptr, ews, st, nullptr, active, fp64);
     if (e) {
       if (err == SS_OK) err = e;
       return false;
@@ -717,10 +786,6 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
     return err == SS_OK;
   };
 
-  if (!eval(pos_dev, S->f, S->smax, V.g, nullptr)) return err;
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, S, P);
-  ok(hipGetLastError(), "k_init");
-
   // ticks, enqueued kDepth ahead; the status word of each tick is copied to
   // pinned memory and read once that tick's event has completed
   constexpr int kDepth = 3;
@@ -728,40 +793,67 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
   hipEvent_t ev[kDepth] = {};
   if (!ok(hipHostMalloc((void**)&flags, sizeof(int32_t) * kDepth, hipHostMallocDefault), "hipHostMalloc")) return err;
   for (int q = 0; q < kDepth && err == SS_OK; ++q) ok(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "event");
-  int64_t tick = 0;
-  while (err == SS_OK) {
-    hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 0, nv, Lay.partial);
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kThreads), 0, st, S, P, 0, dot_blocks, Lay.partial, nullptr,
-                       (int64_t)0);
-    hipLaunchKernelGGL(k_step, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
-    if (!ok(hipGetLastError(), "direction kernels")) break;
-    if (!eval(V.xt, nullptr, nullptr, V.gt, running)) break;  // Phi_t, S_max_t: reduced in k_dots_final
-    hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 1, nv, Lay.partial);
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kThreads), 0, st, S, P, 1, dot_blocks, Lay.partial,
-                       (const double*)(ews + c.off_blk), c.combine_blocks);
-    hipLaunchKernelGGL(k_accept, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
-    if (!ok(hipGetLastError(), "decision kernels")) break;
-    const int q = (int)(tick % kDepth);
-    if (!ok(hipMemcpyAsync(flags + q, running, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag copy")) break;
-    if (!ok(hipEventRecord(ev[q], st), "event record")) break;
-    ++tick;
-    if (tick >= kDepth) {
-      const int w = (int)(tick % kDepth);  // the oldest tick in flight
-      if (!ok(hipEventSynchronize(ev[w]), "event sync")) break;
-      if (flags[w] == 0) break;
+
+  // one stage: a fresh start (history cleared) from the current positions
+  auto run_stage = [&](const MinParams& P, int keep) {
+    if (!eval(pos_dev, S->f, S->smax, V.g, nullptr)) return;
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, S, P, keep);
+    ok(hipGetLastError(), "k_init");
+    int64_t tick = 0;
+    while (err == SS_OK) {
+      hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 0, nv, Lay.partial);
+      hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kThreads), 0, st, S, P, 0, dot_blocks, Lay.partial, nullptr,
+                         (int64_t)0);
+      hipLaunchKernelGGL(k_step, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
+      if (!ok(hipGetLastError(), "direction kernels")) break;
+      if (!eval(V.xt, nullptr, nullptr, V.gt, running)) break;  // Phi_t, S_max_t: reduced in k_dots_final
+      hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 1, nv, Lay.partial);
+      hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kThreads), 0, st, S, P, 1, dot_blocks, Lay.partial,
+                         (const double*)(ews + c.off_blk), c.combine_blocks);
+      hipLaunchKernelGGL(k_accept, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
+      if (!ok(hipGetLastError(), "decision kernels")) break;
+      const int q = (int)(tick % kDepth);
+      if (!ok(hipMemcpyAsync(flags + q, running, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag copy")) break;
+      if (!ok(hipEventRecord(ev[q], st), "event record")) break;
+      ++tick;
+      if (tick >= kDepth) {
+        const int w = (int)(tick % kDepth);  // the oldest tick in flight
+        if (!ok(hipEventSynchronize(ev[w]), "event sync")) break;
+        if (flags[w] == 0) break;
+      }
     }
-  }
-  ok(hipStreamSynchronize(st), "final sync");
+    ok(hipStreamSynchronize(st), "stage sync");
+  };
+
+  // stages: FP64 only, double-double only, or FP64 until it stops (stall, its
+  // own floor or the cap) and then double-double from there, keeping the
+  // kept (s, y) pairs: a restart from steepest descent with the capped step
+  // would need far more halvings than allowed this close to a minimum
   MinState hs;
-  if (err == SS_OK) ok(hipMemcpy(&hs, S, sizeof(MinState), hipMemcpyDeviceToHost), "state copy");
+  int64_t iters_fp64 = 0, evals = 0, iters = 0;
+  const int prec = op->precision;
+  for (int stage = (prec == 0 ? 1 : 0); stage < (prec == 1 ? 1 : 2) && err == SS_OK; ++stage) {
+    fp64 = stage == 0;
+    MinParams P = min_params(op, prob);
+    if (fp64 && prec == 2) P.s_floor = std::max(op->s_floor, op->fp64_floor);
+    P.max_iter = std::max<int64_t>(0, op->max_iter - iters);
+    run_stage(P, (prec == 2 && stage == 1) ? 1 : 0);
+    if (err == SS_OK) ok(hipMemcpy(&hs, S, sizeof(MinState), hipMemcpyDeviceToHost), "state copy");
+    if (err != SS_OK) break;
+    iters += hs.iter;
+    evals += hs.evals;
+    if (fp64) iters_fp64 = hs.iter;
+    if (hs.status == 3) break;  // non-finite: no second stage
+  }
   for (int q = 0; q < kDepth; ++q)
     if (ev[q]) hipEventDestroy(ev[q]);
   hipHostFree(flags);
   if (err != SS_OK) return err;
   out->status = hs.status;
-  out->iters = hs.iter;
-  out->evals = hs.evals;
-  out->grad_evals = hs.evals;
+  out->iters = iters;
+  out->evals = evals;
+  out->grad_evals = evals;
+  out->iters_fp64 = iters_fp64;
   out->phi[0] = hs.f[0];
   out->phi[1] = hs.f[1];
   out->smax[0] = hs.smax[0];

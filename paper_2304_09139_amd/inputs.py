@@ -56,3 +56,21 @@ def uniform_positions(d: int, N: int, seed: int) -> np.ndarray:
 def config_positions(cfg_id: int, d: int, N: int, replica: int = 0) -> np.ndarray:
     """Positions for a named workload and replica (seed = stream_seed(cfg_id, replica))."""
     return uniform_positions(d, N, stream_seed(cfg_id, replica))
+
+
+def batch_shapes(count: int, seed: int = 3, n_min: int = 500, n_max: int = 5000,
+                 dims=(2, 3), chis=(0.2, 0.35, 0.45)) -> list[tuple[int, int, float]]:
+    """A seeded mix of independent quench shapes (d, N, chi): d uniform over
+    ``dims``, N = round(10^U) with U uniform on [log10 n_min, log10 n_max], chi
+    uniform over ``chis`` -- many small independent runs, as in a sweep of
+    Poisson starts."""
+    raw = splitmix64(stream_seed(seed, count), 3 * count).reshape(count, 3)
+    out = []
+    lo, hi = np.log10(n_min), np.log10(n_max)
+    for r in raw:
+        d = dims[int(r[0] % np.uint64(len(dims)))]
+        u = float(r[1] >> np.uint64(11)) * 2.0 ** -53
+        N = int(round(10.0 ** (lo + (hi - lo) * u)))
+        chi = chis[int(r[2] % np.uint64(len(chis)))]
+        out.append((d, N, chi))
+    return out

@@ -36,13 +36,18 @@ class MinOpts(ctypes.Structure):
     _fields_ = [("history", ctypes.c_int32), ("max_iter", ctypes.c_int64), ("s_floor", ctypes.c_double),
                 ("stall_window", ctypes.c_int32), ("stall_ratio", ctypes.c_double), ("c1", ctypes.c_double),
                 ("step_cap", ctypes.c_double), ("max_halvings", ctypes.c_int32),
-                ("max_ls_fail", ctypes.c_int32)]
+                ("max_ls_fail", ctypes.c_int32), ("precision", ctypes.c_int32), ("fp64_floor", ctypes.c_double)]
 
 
 class MinResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int64), ("evals", ctypes.c_int64),
                 ("grad_evals", ctypes.c_int64), ("phi", ctypes.c_double * 2), ("smax", ctypes.c_double * 2),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("iters_fp64", ctypes.c_int64)]
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("max_N", ctypes.c_int64), ("max_M", ctypes.c_int64),
+                ("nk_chunk", ctypes.c_int64), ("grad_k", ctypes.c_int64)]
 
 
 _V = ctypes.c_void_p
@@ -62,11 +67,25 @@ SIGNATURES = {
     "ss_workspace_size": (ctypes.c_int, [_V, ctypes.POINTER(Problem), ctypes.c_int, _SZP]),
     "ss_energy_grad": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V, _V, _V, _V, _V, _V,
                                       ctypes.c_size_t, _V]),
+    "ss_energy_grad_fp64": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V, _V, _V, _V, _V, _V,
+                                           ctypes.c_size_t, _V]),
     "ss_profile_enable": (ctypes.c_int, [_V, ctypes.c_int]),
-    "ss_profile_read": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int, _I64P, ctypes.POINTER(ctypes.c_double)]),
+    "ss_profile_read": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int, _I64P, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
     "ss_minimize": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V, ctypes.POINTER(MinOpts),
                                    ctypes.POINTER(MinResult), _V, ctypes.c_size_t, _V]),
+    "ss_set_tiles": (ctypes.c_int, [_V, ctypes.POINTER(Tile), ctypes.c_int]),
+    "ss_get_tile": (ctypes.c_int, [_V, ctypes.POINTER(Problem), ctypes.POINTER(Tile)]),
+    "ss_batch_workspace_size": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(MinOpts),
+                                               _SZP]),
+    "ss_minimize_batch": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(_V),
+                                         ctypes.POINTER(_V), ctypes.POINTER(MinOpts), ctypes.POINTER(MinResult),
+                                         _V, ctypes.c_size_t, _V]),
 }
+
+DEFAULT_MIN_OPTS = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=50, stall_ratio=0.99, c1=1e-4,
+                        step_cap=1e-2, max_halvings=40, max_ls_fail=3, precision=0, fp64_floor=1e-26)
+PRECISION = {"dd": 0, "fp64": 1, "staged": 2}
 
 
 def lib():
@@ -141,13 +160,20 @@ class Workload:
 class Context:
     """A libss context on one HIP device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tiles: str | list | None = None):
+        """tiles: None (built-in batched tile shapes), "tuned" (the measured table
+        in tiles.json next to this module, if present) or a list of entries."""
         if not torch.cuda.is_available():
             raise RuntimeError("libss needs a HIP device; none is visible")
         self.device = torch.device("cuda", device)
         self._h = ctypes.c_void_p()
         _check(lib().ss_create(device, ctypes.byref(self._h)), what="ss_create")
         self._ws = None
+        if tiles == "tuned":
+            from .tune import load_tiles
+            tiles = load_tiles()
+        if tiles:
+            self.set_tiles(tiles)
 
     def close(self):
         if self._h:
@@ -170,13 +196,15 @@ class Context:
         mask = sum(1 << self.KERNELS[k] for k in kernels) if enable else 0
         self._chk(lib().ss_profile_enable(self._h, mask), "ss_profile_enable")
 
-    def profile_read(self, kernel: str, reset: bool = True) -> tuple[int, float]:
-        """(launches, total milliseconds) of one kernel since the last reset."""
+    def profile_read(self, kernel: str, reset: bool = True, work: bool = False):
+        """(launches, total milliseconds[, work]) of one kernel since the last reset;
+        work = pairs covered (passes) or table entries (table)."""
         n = ctypes.c_int64()
         ms = ctypes.c_double()
+        wk = ctypes.c_double()
         self._chk(lib().ss_profile_read(self._h, self.KERNELS[kernel], 1 if reset else 0, ctypes.byref(n),
-                                        ctypes.byref(ms)), "ss_profile_read")
-        return n.value, ms.value
+                                        ctypes.byref(ms), ctypes.byref(wk)), "ss_profile_read")
+        return (n.value, ms.value, wk.value) if work else (n.value, ms.value)
 
     def wavevectors(self, d: int, R2: int) -> torch.Tensor:
         M = ctypes.c_int64()
@@ -206,8 +234,9 @@ class Context:
         return self._ws
 
     def energy_grad(self, w: Workload, n: torch.Tensor, v: torch.Tensor | None, pos: torch.Tensor,
-                    grad: bool = True, nk: bool = False, out: dict | None = None) -> dict:
-        """Phi, S_max, optionally the gradient [2, d, N] and n~ [4, M] (device tensors)."""
+                    grad: bool = True, nk: bool = False, out: dict | None = None, fp64: bool = False) -> dict:
+        """Phi, S_max, optionally the gradient [2, d, N] and n~ [4, M] (device tensors);
+        fp64=True runs the FP64 passes (results in the dd layout, zero low words)."""
         dev = self.device
         o = out if out is not None else {}
         if "phi" not in o:
@@ -219,18 +248,20 @@ class Context:
             o["nk"] = torch.empty((4, w.M), dtype=torch.float64, device=dev)
         ws = self.workspace(w, 0)
         p = w.problem()
-        self._chk(lib().ss_energy_grad(self._h, ctypes.byref(p), _ptr(n), _ptr(v), _ptr(pos), _ptr(o["phi"]),
-                                       _ptr(o["smax"]), _ptr(o.get("grad") if grad else None),
-                                       _ptr(o.get("nk") if nk else None), _ptr(ws), ws.numel(),
-                                       _stream(dev)), "ss_energy_grad")
+        fn = lib().ss_energy_grad_fp64 if fp64 else lib().ss_energy_grad
+        self._chk(fn(self._h, ctypes.byref(p), _ptr(n), _ptr(v), _ptr(pos), _ptr(o["phi"]),
+                     _ptr(o["smax"]), _ptr(o.get("grad") if grad else None),
+                     _ptr(o.get("nk") if nk else None), _ptr(ws), ws.numel(),
+                     _stream(dev)), "ss_energy_grad")
         return o
 
     def minimize(self, w: Workload, n: torch.Tensor, v: torch.Tensor | None, pos: torch.Tensor,
                  **opts) -> dict:
         """L-BFGS quench of pos (updated in place, [2, d, N]) on the device."""
-        base = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=50, stall_ratio=0.99, c1=1e-4,
-                    step_cap=1e-2, max_halvings=40, max_ls_fail=3)
+        base = dict(DEFAULT_MIN_OPTS)
         base.update(opts)
+        if isinstance(base["precision"], str):
+            base["precision"] = PRECISION[base["precision"]]
         mo = MinOpts(**base)
         res = MinResult()
         ws = self.workspace(w, 1)
@@ -240,4 +271,63 @@ class Context:
                   "ss_minimize")
         return dict(status=STATUS.get(res.status, str(res.status)), iters=res.iters, evals=res.evals,
                     grad_evals=res.grad_evals, phi=(res.phi[0], res.phi[1]), smax=(res.smax[0], res.smax[1]),
-                    seconds=res.seconds)
+                    seconds=res.seconds, iters_fp64=res.iters_fp64)
+
+    # ---- batches ---------------------------------------------------------------
+    def set_tiles(self, tiles: list[dict]) -> None:
+        """Replace the batched tile table: dicts with d, max_N, max_M, nk_chunk, grad_k."""
+        arr = (Tile * max(len(tiles), 1))(*[Tile(t.get("d", 0), t["max_N"], t["max_M"], t["nk_chunk"],
+                                                  t["grad_k"]) for t in tiles])
+        self._chk(lib().ss_set_tiles(self._h, arr, len(tiles)), "ss_set_tiles")
+
+    def get_tile(self, w: Workload) -> dict:
+        t = Tile()
+        p = w.problem()
+        self._chk(lib().ss_get_tile(self._h, ctypes.byref(p), ctypes.byref(t)), "ss_get_tile")
+        return dict(nk_chunk=t.nk_chunk, grad_k=t.grad_k)
+
+    @staticmethod
+    def _batch_args(works, opts_list):
+        n = len(works)
+        probs = (Problem * n)(*[w.problem() for w in works])
+        mos = (MinOpts * n)(*[MinOpts(**o) for o in opts_list])
+        return probs, mos
+
+    def batch_workspace_size(self, works: list[Workload], opts_list: list[dict]) -> int:
+        probs, mos = self._batch_args(works, opts_list)
+        b = ctypes.c_size_t()
+        self._chk(lib().ss_batch_workspace_size(self._h, len(works), probs, mos, ctypes.byref(b)),
+                  "ss_batch_workspace_size")
+        return b.value
+
+    def minimize_batch(self, works: list[Workload], positions: list[torch.Tensor],
+                       weights: list[torch.Tensor | None] | None = None, opts: list[dict] | dict | None = None,
+                       ws: torch.Tensor | None = None) -> list[dict]:
+        """Quench many configurations together (positions updated in place)."""
+        n = len(works)
+        if len(positions) != n:
+            raise ValueError("one position tensor per workload")
+        if opts is None or isinstance(opts, dict):
+            o = dict(DEFAULT_MIN_OPTS)
+            o.update(opts or {})
+            opts_list = [o] * n
+        else:
+            opts_list = []
+            for x in opts:
+                o = dict(DEFAULT_MIN_OPTS)
+                o.update(x)
+                opts_list.append(o)
+        probs, mos = self._batch_args(works, opts_list)
+        need = self.batch_workspace_size(works, opts_list)
+        if ws is None:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        pos_arr = (_V * n)(*[p.data_ptr() for p in positions])
+        v_arr = None
+        if weights is not None:
+            v_arr = (_V * n)(*[(v.data_ptr() if v is not None else None) for v in weights])
+        res = (MinResult * n)()
+        self._chk(lib().ss_minimize_batch(self._h, n, probs, v_arr, pos_arr, mos, res, _ptr(ws), ws.numel(),
+                                          _stream(self.device)), "ss_minimize_batch")
+        return [dict(status=STATUS.get(r.status, str(r.status)), iters=r.iters, evals=r.evals,
+                     grad_evals=r.grad_evals, phi=(r.phi[0], r.phi[1]), smax=(r.smax[0], r.smax[1]),
+                     seconds=r.seconds, iters_fp64=r.iters_fp64) for r in res]

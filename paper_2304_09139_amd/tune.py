@@ -1,0 +1,84 @@
+"""Measure the batched tile shapes and write the tile table (tiles.json).
+
+The batched launches split each configuration's n~(k) pass into units of
+`nk_chunk` particles and its gradient pass into blocks of `grad_k`
+wavevectors.  Both are looked up by (d, N, M) in the context's tile table.  For
+every bucket of (d, N) this script quenches a seeded batch of configurations
+of that bucket for a fixed number of L-BFGS iterations with every candidate
+shape, and keeps the shape with the highest pair throughput.
+
+    python -m paper_2304_09139_amd.tune [--out tiles.json] [--count 48] [--iters 12]
+
+Changing the table changes batched results in their last bits (the reduction
+order follows the tile), so a table is fixed before production runs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TILES_PATH = os.path.join(HERE, "tiles.json")
+
+NK_CHUNKS = (32, 64, 128, 256)
+GRAD_KS = (256, 512, 1024, 2048)
+# (d, N range) buckets; M follows from chi in {0.2, 0.35, 0.45}
+BUCKETS = [(2, 500, 1000), (2, 1000, 2000), (2, 2000, 5000), (3, 500, 1000), (3, 1000, 2000), (3, 2000, 5000)]
+
+
+def load_tiles(path: str = TILES_PATH) -> list[dict]:
+    """The committed tile table, or [] when there is none."""
+    if not os.path.exists(path):
+        return []
+    with open(path) as fh:
+        return json.load(fh)["tiles"]
+
+
+def tune(count: int = 48, iters: int = 12, out: str = TILES_PATH) -> list[dict]:
+    import torch
+
+    from . import inputs, ss
+
+    ctx = ss.Context(0)
+    entries = []
+    for d, n_lo, n_hi in BUCKETS:
+        shapes = inputs.batch_shapes(count, seed=100 + d * 10 + n_lo // 500, n_min=n_lo, n_max=n_hi, dims=(d,))
+        works = [ss.Workload.from_chi(dd, N, chi) for dd, N, chi in shapes]
+        starts = [inputs.config_positions(7, w.d, w.N, i) for i, w in enumerate(works)]
+        best = None
+        for nk_chunk in NK_CHUNKS:
+            for grad_k in GRAD_KS:
+                ctx.set_tiles([dict(d=0, max_N=1 << 40, max_M=1 << 40, nk_chunk=nk_chunk, grad_k=grad_k)])
+                rate = []
+                for rep in range(2):
+                    xs = [torch.from_numpy(p).cuda() for p in starts]
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    res = ctx.minimize_batch(works, xs, opts=dict(max_iter=iters, s_floor=0.0))
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    pairs = sum(w.M * w.N * r["evals"] for w, r in zip(works, res))
+                    rate.append(pairs / dt)
+                r = max(rate)
+                print(f"d={d} N=[{n_lo},{n_hi}) nk_chunk={nk_chunk} grad_k={grad_k}: {r:.3e} pairs/s", flush=True)
+                if best is None or r > best[0]:
+                    best = (r, nk_chunk, grad_k)
+        max_M = max(w.M for w in works)
+        entries.append(dict(d=d, max_N=n_hi, max_M=1 << 40, nk_chunk=best[1], grad_k=best[2],
+                            pairs_per_s=best[0], max_M_seen=max_M))
+    ctx.close()
+    with open(out, "w") as fh:
+        json.dump({"tiles": entries, "count": count, "iters": iters}, fh, indent=1)
+    return entries
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TILES_PATH)
+    ap.add_argument("--count", type=int, default=48)
+    ap.add_argument("--iters", type=int, default=12)
+    a = ap.parse_args()
+    for e in tune(a.count, a.iters, a.out):
+        print(json.dumps(e))

@@ -115,8 +115,9 @@ def lbfgs_mp(fg, x0, nmean, max_iter, history=8, c1=1e-4, step_cap=1e-2, max_hal
 
     fg(x) -> (f, g list).  Returns (x, list of f at each iterate).  Rules: the
     two-loop recursion with H0 = (s.y / y.y) I of the newest pair; a
-    steepest-descent step scaled to move at most step_cap * nmean when the
-    history is empty or the direction is not a descent direction; Armijo
+    steepest-descent step scaled to move at most step_cap * nmean, and at most
+    to 2 f / g.g (the minimum value is 0), when the history is empty or the
+    direction is not a descent direction; Armijo
     backtracking by halving from alpha = 1; a pair is kept only when s.y > 0.
     """
     x = list(x0)
@@ -144,7 +145,7 @@ def lbfgs_mp(fg, x0, nmean, max_iter, history=8, c1=1e-4, step_cap=1e-2, max_hal
         if p is None:
             S, Y, R = [], [], []
             gmax = max(abs(gi) for gi in g)
-            scale = ctx.mpf(step_cap * nmean) / gmax
+            scale = min(ctx.mpf(step_cap * nmean) / gmax, 2 * f / sum(gi * gi for gi in g))
             p = [-gi * scale for gi in g]
             gp = sum(a * b for a, b in zip(g, p))
         alpha = ctx.mpf(1)
