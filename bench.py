@@ -39,9 +39,14 @@ PEAK_FP64_OPS = 256 * 64 * 2.4e9
 WORKLOADS = {
     "d3_N8000_chi0.45": dict(d=3, N=8000, chi=0.45, cfg_id=2),
     "d3_N30000_chi0.45": dict(d=3, N=30000, chi=0.45, cfg_id=4),
+    # the same size with v(k) = (1 - |k|/K)^2, K^2 = (R2 + 1/2) (2 pi / L)^2
+    "d3_N30000_chi0.45_w": dict(d=3, N=30000, chi=0.45, cfg_id=4, vkind=1),
     "d2_N128_chi0.4": dict(d=2, N=128, chi=0.4, cfg_id=1),
     # 256 independent quenches: d in {2, 3}, N log-uniform in [500, 5000], chi in {0.2, 0.35, 0.45}
     "batch256_d2-3_N500-5000": dict(batch=256, shape_seed=3, cfg_id=3),
+    # 200 requests served with continuous batching: d in {2, 3}, N log-uniform in
+    # [500, 5000], chi uniform in [0.1, 0.49], Poisson arrivals at 0.7 x capacity
+    "serve200_d2-3_N500-5000": dict(serve=200, stream_seed=5, cfg_id=6),
 }
 
 
@@ -107,6 +112,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="d3_N8000_chi0.45", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--progress", type=float, default=30.0,
+                    help="seconds between the library's progress lines on stderr (0: none)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched workloads: skip timing the same configurations one at a time")
+    ap.add_argument("--precision", default="dd", choices=("dd", "staged", "fp64"),
+                    help="evaluation precision of the quench (staged: FP64 until it stalls, then dd)")
     ap.add_argument("--evals", type=int, default=0,
                     help="instead of quenches, run this many Phi + gradient evaluations of the first start and "
                          "then one 1 GiB device copy (the calibration kernel for the HBM counters)")
@@ -126,21 +137,27 @@ def main():
     wl = WORKLOADS[args.workload]
     if "batch" in wl:
         return bench_batch(args, wl)
+    if "serve" in wl:
+        return bench_serve(args, wl)
     d, N, chi = wl["d"], wl["N"], wl["chi"]
     ctx = ss.Context(0)
-    w = ss.Workload.from_chi(d, N, chi)
+    ctx.progress(args.progress)
+    vkind = wl.get("vkind", 0)
+    w = ss.Workload.from_chi(d, N, chi, vkind=vkind)
     n = ctx.wavevectors(d, w.R2)
+    v = ctx.weights(w, n) if vkind else None
+    mopts = dict(s_floor=FLOOR, precision=args.precision)
     # all starting configurations resident in HBM before the timed region
     starts = [torch.from_numpy(inputs.config_positions(wl["cfg_id"], d, N, r)).cuda()
               for r in range(args.warmup + args.steps)]
     ctx.workspace(w, 1)
     torch.cuda.synchronize()
     if args.evals > 0:
-        out = ctx.energy_grad(w, n, None, starts[0], grad=True)
+        out = ctx.energy_grad(w, n, v, starts[0], grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.evals):
-            ctx.energy_grad(w, n, None, starts[0], grad=True, out=out)
+            ctx.energy_grad(w, n, v, starts[0], grad=True, out=out)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
@@ -154,7 +171,7 @@ def main():
         ctx.close()
         return
     for r in range(args.warmup):
-        ctx.minimize(w, n, None, starts[r], s_floor=FLOOR)
+        ctx.minimize(w, n, v, starts[r], **mopts)
     torch.cuda.synchronize()
     # inside the timed region only the roofline kernel carries timing events
     ctx.profile(True, kernels=("grad",))
@@ -163,17 +180,25 @@ def main():
     t0 = time.perf_counter()
     results = []
     for r in range(args.warmup, args.warmup + args.steps):
-        results.append(ctx.minimize(w, n, None, starts[r], s_floor=FLOOR))
+        results.append(ctx.minimize(w, n, v, starts[r], **mopts))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {"grad": ctx.profile_read("grad", reset=True)}
+    if args.precision != "dd":   # double-double gradient launches timed on their own
+        ctx.profile(True, kernels=("grad",))
+        ctx.profile_read("grad", reset=True)
+        out_g = ctx.energy_grad(w, n, v, starts[0], grad=True)
+        for _ in range(9):
+            ctx.energy_grad(w, n, v, starts[0], grad=True, out=out_g)
+        torch.cuda.synchronize()
+        prof["grad_dd"] = ctx.profile_read("grad", reset=True)
     # per-pass times of a plain evaluation (outside the timed region)
     ctx.profile(True)
     for k in ("nk", "table"):
         ctx.profile_read(k, reset=True)
-    out_e = ctx.energy_grad(w, n, None, starts[0], grad=True)
+    out_e = ctx.energy_grad(w, n, v, starts[0], grad=True)
     for _ in range(9):
-        ctx.energy_grad(w, n, None, starts[0], grad=True, out=out_e)
+        ctx.energy_grad(w, n, v, starts[0], grad=True, out=out_e)
     torch.cuda.synchronize()
     prof["nk"] = ctx.profile_read("nk", reset=True)
     prof["table"] = ctx.profile_read("table", reset=True)
@@ -186,7 +211,12 @@ def main():
     converged = sum(1 for r in results if r["status"] == "converged")
     launches, ms = prof["grad"]
     avg_s = ms / launches * 1e-3
-    achieved = OPS_PER_PAIR["grad"] * w.M * N / avg_s
+    # the roofline is that of the double-double gradient pass: in a staged run
+    # the FP64 launches are left out of the average
+    if args.precision != "dd":
+        launches, ms = prof["grad_dd"]
+        avg_s = ms / max(launches, 1) * 1e-3
+    achieved = OPS_PER_PAIR["grad"] * w.M * N / avg_s if launches else 0.0
     traffic = read_traffic("k_grad", args.workload)
     nk_l, nk_ms = prof["nk"]
     out = {
@@ -200,15 +230,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "dd",
+        "dtype": {"dd": "dd", "staged": "f64 then dd", "fp64": "f64"}[args.precision],
         "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
-        "config": {"workload": f"L-BFGS quench to S_max <= {FLOOR:g}, d={d}, N={N}, chi={chi}, v(k)=1",
-                   "d": d, "N": N, "chi": chi, "R2": w.R2, "M": w.M, "s_floor": FLOOR,
-                   "parallelism": "single GPU"},
+        "config": {"workload": f"L-BFGS quench to S_max <= {FLOOR:g}, d={d}, N={N}, chi={chi}, "
+                               + ("v(k)=(1-|k|/K)^2" if vkind else "v(k)=1")
+                               + ("" if args.precision == "dd" else f", {args.precision} precision"),
+                   "d": d, "N": N, "chi": chi, "R2": w.R2, "M": w.M, "s_floor": FLOOR, "vkind": vkind,
+                   "precision": args.precision, "parallelism": "single GPU"},
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{args.steps}",
         "smax_worst": max(r["smax"][0] for r in results),
         "iters_mean": sum(r["iters"] for r in results) / len(results),
+        "iters_fp64_mean": sum(r["iters_fp64"] for r in results) / len(results),
         "evals_mean": evals / len(results),
         "eval_ms_nk_pass": nk_ms / max(nk_l, 1),
         "eval_ms_grad_pass": ms / max(launches, 1),
@@ -243,7 +276,10 @@ def bench_batch(args, wl):
 
     count = wl["batch"]
     shapes = inputs.batch_shapes(count, seed=wl["shape_seed"])
-    ctx = ss.Context(0)
+    from paper_2304_09139_amd.tune import load_tiles
+
+    ctx_tuned = bool(load_tiles())
+    ctx = ss.Context(0, tiles="tuned")
     works = [ss.Workload.from_chi(d, N, chi) for d, N, chi in shapes]
     steps = args.steps if args.steps_set else 2
     starts = [[torch.from_numpy(inputs.config_positions(wl["cfg_id"], w.d, w.N, 1000 * r + i)).cuda()
@@ -267,17 +303,19 @@ def bench_batch(args, wl):
     ctx.profile(False)
     pairs = sum(w.M * w.N * r["evals"] for w, r in zip(works * steps, results))
     converged = sum(1 for r in results if r["status"] == "converged")
-    # one at a time (first step's starts again, fresh copies), timed once
-    seq = [torch.from_numpy(inputs.config_positions(wl["cfg_id"], w.d, w.N, 1000 * args.warmup + i)).cuda()
-           for i, w in enumerate(works)]
-    wsn = [ctx.wavevectors(w.d, w.R2) for w in works]
-    ctx.workspace(max(works, key=lambda w: ctx.workspace_size(w, 1)), 1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    seq_res = [ctx.minimize(w, n, None, x, **opts) for w, n, x in zip(works, wsn, seq)]
-    torch.cuda.synchronize()
-    seq_elapsed = time.perf_counter() - t1
-    seq_conv = sum(1 for r in seq_res if r["status"] == "converged")
+    seq_conv, seq_elapsed = 0, float("nan")
+    if not args.no_sequential:
+        # one at a time (first step's starts again, fresh copies), timed once
+        seq = [torch.from_numpy(inputs.config_positions(wl["cfg_id"], w.d, w.N, 1000 * args.warmup + i)).cuda()
+               for i, w in enumerate(works)]
+        wsn = [ctx.wavevectors(w.d, w.R2) for w in works]
+        ctx.workspace(max(works, key=lambda w: ctx.workspace_size(w, 1)), 1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        seq_res = [ctx.minimize(w, n, None, x, **opts) for w, n, x in zip(works, wsn, seq)]
+        torch.cuda.synchronize()
+        seq_elapsed = time.perf_counter() - t1
+        seq_conv = sum(1 for r in seq_res if r["status"] == "converged")
     achieved = OPS_PER_PAIR["grad"] * gpairs / (gms * 1e-3) if gms > 0 else 0.0
     lat = sorted(r["seconds"] for r in results[-count:])
     out = {
@@ -299,9 +337,10 @@ def bench_batch(args, wl):
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{len(results)}",
         "smax_worst": max(r["smax"][0] for r in results),
-        "one_at_a_time": {"configs_per_s": seq_conv / seq_elapsed, "seconds": seq_elapsed,
-                          "converged": f"{seq_conv}/{count}"},
-        "speedup_vs_one_at_a_time": (converged / elapsed) / (seq_conv / seq_elapsed),
+        "one_at_a_time": None if args.no_sequential else {
+            "configs_per_s": seq_conv / seq_elapsed, "seconds": seq_elapsed, "converged": f"{seq_conv}/{count}"},
+        "speedup_vs_one_at_a_time": None if args.no_sequential else (converged / elapsed) / (seq_conv / seq_elapsed),
+        "tiles": "tuned table" if ctx_tuned else "built-in",
         "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(0.99 * len(lat)))],
                       "max": lat[-1]},
         "roofline": {
@@ -316,6 +355,86 @@ def bench_batch(args, wl):
                         f"listed in each launch; peak = 256 CU x 64 lanes x 2.4 GHz",
             "launches": launches,
         },
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_serve(args, wl):
+    """Served quenches: the request stream is first submitted all at once (the
+    capacity, configs/s), then again with Poisson arrivals at 0.7 x that capacity;
+    latencies are from ss_submit until the result was copied out."""
+    import numpy as np
+
+    from paper_2304_09139_amd import inputs, ss
+    from paper_2304_09139_amd.tune import load_tiles
+
+    count = wl["serve"]
+    stream = inputs.serve_stream(count, seed=wl["stream_seed"])
+    works = [ss.Workload.from_chi(d, N, chi) for d, N, chi, _ in stream]
+    starts = [inputs.config_positions(wl["cfg_id"], w.d, w.N, i) for i, w in enumerate(works)]
+    ctx = ss.Context(0, tiles="tuned")
+    arena = 8 << 30
+    ctx.server_start(arena, max_slots=512)
+
+    def run(times):
+        """Submit request i at times[i] (seconds from the start), collect all."""
+        t0 = time.perf_counter()
+        tickets = []
+        done = {}
+        i = 0
+        while len(done) < count:
+            now = time.perf_counter() - t0
+            while i < count and times[i] <= now:
+                tickets.append(ctx.submit(works[i], starts[i], s_floor=FLOOR))
+                i += 1
+            for k, t in enumerate(tickets):
+                if k not in done:
+                    r = ctx.poll(t)
+                    if r is not None:
+                        done[k] = r[0]
+            time.sleep(0.0005)
+        return time.perf_counter() - t0, [done[k] for k in range(count)]
+
+    # warm-up: a few short requests (server buffers, first launches)
+    warm = [ctx.submit(works[i], starts[i], max_iter=2) for i in range(min(count, 8))]
+    for t in warm:
+        while ctx.poll(t) is None:
+            time.sleep(0.001)
+    closed_s, closed = run([0.0] * count)
+    cap = sum(1 for r in closed if r["status"] == "converged") / closed_s
+    lam = 0.7 * cap
+    open_s, opened = run([t / lam for *_, t in stream])
+    ctx.server_stop()
+    lat = np.array([r["seconds"] for r in opened])
+    pairs = sum(w.M * w.N * r["evals"] for w, r in zip(works, opened))
+    conv = sum(1 for r in opened if r["status"] == "converged")
+    out = {
+        "metric": "dd particle-wavevector pairs/s (Phi+grad) and configs/s at stated max S(k) floor",
+        "value": pairs / open_s,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": open_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "dd",
+        "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
+        "config": {"workload": f"{count} served L-BFGS quenches to S_max <= {FLOOR:g}, d in {{2,3}}, "
+                               f"N log-uniform in [500, 5000], chi uniform in [0.1, 0.49], Poisson arrivals "
+                               f"at 0.7 x capacity", "requests": count, "s_floor": FLOOR,
+                   "parallelism": "single GPU"},
+        "configs_per_s": conv / open_s,
+        "converged": f"{conv}/{count}",
+        "capacity_configs_per_s": cap,
+        "arrival_rate_per_s": lam,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "closed_batch_latency_s": {"p50": float(np.percentile([r["seconds"] for r in closed], 50)),
+                                   "p99": float(np.percentile([r["seconds"] for r in closed], 99))},
+        "tiles": "tuned table" if load_tiles() else "built-in",
     }
     print(json.dumps(out), flush=True)
     ctx.close()

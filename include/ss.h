@@ -142,6 +142,12 @@ int ss_energy_grad_fp64(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_de
                         const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Progress lines for long runs (off by default): with seconds > 0, ss_minimize
+ * prints its stage, iteration, evaluations, Phi and S_max to stderr at most
+ * this often, and ss_minimize_batch the number of configurations still
+ * running.  0 turns them off; SS_EINVAL for a negative or non-finite value. */
+int ss_set_progress(ss_ctx* ctx, double seconds);
+
 /* Per-kernel timing for measurement (off by default).  `mask` selects the
  * kernels: bit 0 the n~(k) pass (kernel 0), bit 1 the gradient pass (kernel 1),
  * bit 2 the phase-table kernel (kernel 2); 0 turns timing off.  Every launch of
@@ -269,6 +275,59 @@ int ss_batch_workspace_size(ss_ctx* ctx, int count, const ss_problem* probs, con
 int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs, const double* const* v_dev,
                       double* const* pos_dev, const ss_min_opts* opts, ss_min_result* out, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* ---- Serving: continuous batching of quench requests ----------------------
+ * A server on a context runs a worker thread with its own HIP stream that
+ * keeps one batched minimiser step in flight over every configuration it is
+ * running.  Requests wait in submission order; at step boundaries the worker
+ * admits as many as there are free slots and room in the caller's device
+ * arena (first fit), runs their starting evaluation, and adds them to the work
+ * lists; stopped configurations are copied out and their slot and arena space
+ * reused.  Launch shapes come from the tile table by (d, N, M) alone, so a
+ * request's result is bitwise the same whatever else is being served and equal
+ * to ss_minimize_batch's result for it.  ss_submit and ss_poll may be called
+ * from any thread.  Do not change the tile table while a server runs. */
+
+/* One quench request.  The starting positions are copied by ss_submit. */
+typedef struct {
+  int32_t d;               /* 1..4                                                     */
+  int64_t N;               /* particles                                                */
+  int64_t R2;              /* cutoff |n|^2 <= R2 (ss_cutoff gives it from chi)          */
+  double L;                /* box side                                                 */
+  int32_t vkind;           /* 0: v = 1; 1: v = (1 - |k|/K)^2, computed by the library   */
+  const double* pos_host;  /* double[2][d][N] fractional starting positions (host)      */
+  ss_min_opts opts;        /* minimiser options; precision must be 0                   */
+} ss_request;
+
+/* Start the server.  arena_dev: caller-owned device memory that holds every
+ * running configuration's workspace (ss_batch_workspace_size of a single
+ * problem gives the order of magnitude; a request that cannot fit even in
+ * an empty arena fails with SS_ENOMEM at ss_poll); max_slots: the most
+ * configurations run at once (1..65536).  The server also allocates its
+ * descriptor arrays and work lists (a few MB).  SS_ESTATE if one already runs
+ * on this context. */
+int ss_server_start(ss_ctx* ctx, void* arena_dev, size_t arena_bytes, int max_slots);
+
+/* Queue one request; *ticket identifies it for ss_poll.  Non-blocking apart
+ * from building the wavevector plan of a new (d, R2) on first use.  SS_EINVAL
+ * for an invalid request (shape, vkind, options, NULL or non-finite positions),
+ * SS_ESTATE without a running server or while it stops, or the server's error
+ * after a failure. */
+int ss_submit(ss_ctx* ctx, const ss_request* req, uint64_t* ticket);
+
+/* SS_PENDING while the request is queued or running.  When it is done: fills
+ * *out (seconds = from ss_submit until the result was copied out), copies the
+ * final positions to pos_host_out (double[2][d][N], if not NULL), forgets the
+ * ticket and returns SS_OK (the quench's own outcome is out->status).
+ * SS_ENOTFOUND for an unknown or already collected ticket; a failed request
+ * returns its error (SS_ENOMEM: larger than the arena). */
+int ss_poll(ss_ctx* ctx, uint64_t ticket, ss_min_result* out, double* pos_host_out);
+
+/* Stop accepting requests, finish every queued and running one, stop the
+ * worker and release the server; results not yet collected with ss_poll are
+ * dropped.  Returns the server's error, if any (SS_OK if none runs).
+ * ss_destroy stops a running server. */
+int ss_server_stop(ss_ctx* ctx);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["ss_kernels.hip", "ss_fp64.hip", "ss_api.hip", "ss_lbfgs.hip", "ss_batch.hip"]
+SOURCES = ["ss_kernels.hip", "ss_fp64.hip", "ss_api.hip", "ss_lbfgs.hip", "ss_batch.hip", "ss_server.hip"]
 LIB = os.path.join(HERE, "libss.so")
 ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
 

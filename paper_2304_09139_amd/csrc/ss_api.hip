@@ -439,6 +439,7 @@ hipEvent_t prof_event(ss_ctx* ctx) {
 
 hipEvent_t prof_begin(ss_ctx* ctx, int which, hipStream_t st) {
   if (!(ctx->prof.mask & (1 << which))) return nullptr;
+  std::lock_guard<std::mutex> g(ctx->prof.mu);
   hipEvent_t a = prof_event(ctx);
   if (a && hipEventRecord(a, st) != hipSuccess) {
     ctx->prof.pool.push_back(a);
@@ -448,6 +449,7 @@ hipEvent_t prof_begin(ss_ctx* ctx, int which, hipStream_t st) {
 }
 
 void prof_end(ss_ctx* ctx, int which, hipStream_t st, hipEvent_t a, double work) {
+  std::lock_guard<std::mutex> g(ctx->prof.mu);
   hipEvent_t b = prof_event(ctx);
   if (!b || hipEventRecord(b, st) != hipSuccess) {
     ctx->prof.pool.push_back(a);
@@ -519,6 +521,7 @@ int ss_create(int device, ss_ctx** out) {
 
 int ss_destroy(ss_ctx* ctx) {
   if (!ctx) return SS_OK;
+  if (ctx->server) ss_server_stop(ctx);
   hipSetDevice(ctx->device);
   for (auto& kv : ctx->plans) {
     Plan* pl = kv.second;
@@ -637,6 +640,12 @@ int ss_workspace_size(ss_ctx* ctx, const ss_problem* prob, int op, size_t* bytes
   return SS_OK;
 }
 
+int ss_set_progress(ss_ctx* ctx, double seconds) {
+  if (!ctx || !(seconds >= 0.0) || !isfinite(seconds)) return SS_EINVAL;
+  ctx->progress_interval = seconds;
+  return SS_OK;
+}
+
 int ss_profile_enable(ss_ctx* ctx, int mask) {
   if (!ctx || mask < 0 || mask > 7) return SS_EINVAL;
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -646,7 +655,7 @@ int ss_profile_enable(ss_ctx* ctx, int mask) {
 
 int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, double* total_ms, double* work) {
   if (!ctx || !launches || !total_ms || kernel < 0 || kernel > 2) return SS_EINVAL;
-  std::lock_guard<std::mutex> g(ctx->mu);
+  std::lock_guard<std::mutex> g(ctx->prof.mu);
   auto& v = ctx->prof.ev[kernel];
   double tot = 0.0, wk = 0.0;
   for (auto& pr : v) {

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -28,31 +29,10 @@
 #include "ss.h"
 #include "ss_internal.h"
 #include "ss_min.h"
+#include "ss_engine.h"
 
 namespace ss {
-int prepare_tiled(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg, Plan::NkSched** sc,
-                  int32_t** chunk_begin);
-TileSpec tile_for(ss_ctx* ctx, int d, int64_t N, int64_t M);
-bool min_opts_valid(const ss_min_opts* op);
-MinParams min_params(const ss_min_opts* op, const ss_problem* prob);
-
-hipError_t launch_batch_table(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
-                              hipStream_t st);
-hipError_t launch_batch_nk(int d, int pt, int R1max, const EvalSlot* es, const BUnit* units, int64_t n, int gate,
-                           hipStream_t st);
-hipError_t launch_batch_combine(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
-hipError_t launch_batch_final(const EvalSlot* es, const int32_t* list, int64_t n, hipStream_t st);
-hipError_t launch_batch_grad(int d, const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
-hipError_t launch_batch_gcomb(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
-                              hipStream_t st);
-hipError_t launch_batch_dots(const MinSlot* ms, const BUnit* units, int64_t n, int mode, hipStream_t st);
-hipError_t launch_batch_dots_final(const MinSlot* ms, const int32_t* list, int64_t n, int mode, hipStream_t st);
-hipError_t launch_batch_step(const MinSlot* ms, const BUnit* units, int64_t n, hipStream_t st);
-hipError_t launch_batch_accept(const MinSlot* ms, const BUnit* units, int64_t n, hipStream_t st);
-hipError_t launch_batch_init(const MinSlot* ms, const int32_t* list, int64_t n, hipStream_t st);
-hipError_t launch_batch_flags(const MinSlot* ms, const int32_t* list, int64_t n, int32_t* out, hipStream_t st);
-
-namespace {
+namespace eng {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -64,35 +44,6 @@ size_t min_bytes(int64_t nv, int m, int G) {
   const size_t vec = al256(sizeof(double) * 2 * (size_t)nv);
   return vec * (4 + 2 * (size_t)(m + 1)) + al256(sizeof(MinState)) + al256(sizeof(double) * 2 * (2 * m + 2) * G);
 }
-
-struct HostSlot {
-  ss_problem prob;
-  ss_min_opts opts;
-  Plan* pl = nullptr;
-  LaunchCfg c{};
-  Plan::NkSched* sc = nullptr;
-  int32_t* cb = nullptr;
-  int64_t nv = 0;
-  int m = 0, G = 0;
-  size_t bytes = 0;  // workspace of this configuration (energy + minimiser)
-  // unit counts of this configuration's grids
-  int64_t n_table = 0, n_nk = 0, n_comb = 0, n_grad = 0, n_gcomb = 0, n_dots = 0, n_vec = 0;
-  double work = 0.0;  // M N, for ordering
-};
-
-// offsets and counts of each batched launch inside the unit array
-struct Lists {
-  struct Group {
-    int d, pt, R1max;
-    int64_t off, n;
-    double pairs;  // M N summed over the group's configurations
-  };
-  double table_work = 0.0;
-  int64_t table_off = 0, table_n = 0, comb_off = 0, comb_n = 0, gcomb_off = 0, gcomb_n = 0;
-  int64_t dots_off = 0, dots_n = 0, vec_off = 0, vec_n = 0;
-  std::vector<Group> nk, grad;
-  int64_t nlist = 0;
-};
 
 int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot* h) {
   int rc = prepare_tiled(ctx, p, &h->pl, &h->c, &h->sc, &h->cb);
@@ -176,6 +127,7 @@ void build_lists(const std::vector<HostSlot>& hs, std::vector<int> active, std::
   for (int s : active) add(hs[s].n_vec, s);
   L.vec_n = (int64_t)U.size() - L.vec_off;
 }
+
 
 // device-side header of the batch workspace
 struct Header {
@@ -270,6 +222,43 @@ void fill_slot(const HostSlot& h, char* mem, double* x, const double* v, EvalSlo
   E->running = &C->S->running;
 }
 
+hipError_t launch_eval(ss_ctx* ctx, const DevArrays& D, const Lists& L, int which, int gate, hipStream_t st) {
+  hipError_t e = timed(ctx, 2, st, L.table_work,
+                       [&] { return launch_batch_table(D.es, D.units + L.table_off, L.table_n, which, gate, st); });
+  if (e != hipSuccess) return e;
+  for (const auto& g : L.nk) {
+    e = timed(ctx, 0, st, g.pairs,
+              [&] { return launch_batch_nk(g.d, g.pt, g.R1max, D.es, D.units + g.off, g.n, gate, st); });
+    if (e != hipSuccess) return e;
+  }
+  e = launch_batch_combine(D.es, D.units + L.comb_off, L.comb_n, gate, st);
+  if (e != hipSuccess) return e;
+  for (const auto& g : L.grad) {
+    e = timed(ctx, 1, st, g.pairs, [&] { return launch_batch_grad(g.d, D.es, D.units + g.off, g.n, gate, st); });
+    if (e != hipSuccess) return e;
+  }
+  return launch_batch_gcomb(D.es, D.units + L.gcomb_off, L.gcomb_n, which, gate, st);
+}
+
+hipError_t launch_start(ss_ctx* ctx, const DevArrays& D, const Lists& L, hipStream_t st) {
+  hipError_t e = launch_eval(ctx, D, L, 0, 0, st);
+  if (e == hipSuccess) e = launch_batch_final(D.es, D.list, L.nlist, st);
+  if (e == hipSuccess) e = launch_batch_init(D.ms, D.list, L.nlist, st);
+  return e;
+}
+
+hipError_t launch_tick(ss_ctx* ctx, const DevArrays& D, const Lists& L, hipStream_t st) {
+  hipError_t e = launch_batch_dots(D.ms, D.units + L.dots_off, L.dots_n, 0, st);
+  if (e == hipSuccess) e = launch_batch_dots_final(D.ms, D.list, L.nlist, 0, st);
+  if (e == hipSuccess) e = launch_batch_step(D.ms, D.units + L.vec_off, L.vec_n, st);
+  if (e == hipSuccess) e = launch_eval(ctx, D, L, 1, 1, st);
+  if (e == hipSuccess) e = launch_batch_dots(D.ms, D.units + L.dots_off, L.dots_n, 1, st);
+  if (e == hipSuccess) e = launch_batch_dots_final(D.ms, D.list, L.nlist, 1, st);
+  if (e == hipSuccess) e = launch_batch_accept(D.ms, D.units + L.vec_off, L.vec_n, st);
+  if (e == hipSuccess) e = launch_batch_flags(D.ms, D.list, L.nlist, D.flags, st);
+  return e;
+}
+
 struct Pinned {
   void* p = nullptr;
   ~Pinned() {
@@ -311,10 +300,11 @@ int setup_all(ss_ctx* ctx, int count, const ss_problem* probs, const ss_min_opts
   return SS_OK;
 }
 
-}  // namespace
+}  // namespace eng
 }  // namespace ss
 
 using namespace ss;
+using namespace ss::eng;
 
 extern "C" int ss_set_tiles(ss_ctx* ctx, const ss_tile* tiles, int count) {
   if (!ctx || count < 0 || (count > 0 && !tiles)) return SS_EINVAL;
@@ -438,40 +428,16 @@ extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs
     up_pending = true;
     return err == SS_OK;
   };
-  auto eval = [&](int which, int gate) {
-    ok(timed(ctx, 2, st, L.table_work,
-             [&] { return launch_batch_table(H.es, H.units + L.table_off, L.table_n, which, gate, st); }),
-       "batched table");
-    for (const auto& g : L.nk)
-      ok(timed(ctx, 0, st, g.pairs,
-               [&] { return launch_batch_nk(g.d, g.pt, g.R1max, H.es, H.units + g.off, g.n, gate, st); }),
-         "batched n(k)");
-    ok(launch_batch_combine(H.es, H.units + L.comb_off, L.comb_n, gate, st), "batched combine");
-    for (const auto& g : L.grad)
-      ok(timed(ctx, 1, st, g.pairs, [&] { return launch_batch_grad(g.d, H.es, H.units + g.off, g.n, gate, st); }),
-         "batched gradient");
-    ok(launch_batch_gcomb(H.es, H.units + L.gcomb_off, L.gcomb_n, which, gate, st), "batched gradient combine");
-    return err == SS_OK;
-  };
-
+  const DevArrays D{H.es, H.ms, H.units, H.list, H.flags};
   std::vector<int> active(count);
   std::iota(active.begin(), active.end(), 0);
   std::vector<double> t_stop(count, -1.0);
   // the starting evaluation and the first tests of every configuration
-  if (upload(active) && eval(0, 0)) {
-    ok(launch_batch_final(H.es, H.list, L.nlist, st), "batched final");
-    ok(launch_batch_init(H.ms, H.list, L.nlist, st), "batched init");
-  }
+  if (upload(active)) ok(launch_start(ctx, D, L, st), "batched start");
   int64_t tick = 0;
+  double last_print = 0.0;
   while (err == SS_OK) {
-    ok(launch_batch_dots(H.ms, H.units + L.dots_off, L.dots_n, 0, st), "batched dots");
-    ok(launch_batch_dots_final(H.ms, H.list, L.nlist, 0, st), "batched direction");
-    ok(launch_batch_step(H.ms, H.units + L.vec_off, L.vec_n, st), "batched step");
-    if (!eval(1, 1)) break;
-    ok(launch_batch_dots(H.ms, H.units + L.dots_off, L.dots_n, 1, st), "batched dots");
-    ok(launch_batch_dots_final(H.ms, H.list, L.nlist, 1, st), "batched decision");
-    ok(launch_batch_accept(H.ms, H.units + L.vec_off, L.vec_n, st), "batched accept");
-    ok(launch_batch_flags(H.ms, H.list, L.nlist, H.flags, st), "batched flags");
+    if (!ok(launch_tick(ctx, D, L, st), "batched step")) break;
     const int q = (int)(tick % kDepth);
     int32_t* hf = (int32_t*)pin_flags.p + (size_t)q * count;
     if (!ok(hipMemcpyAsync(hf, H.flags, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st), "flag copy")) break;
@@ -488,6 +454,12 @@ extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs
     for (int s : active) {
       if (f[s]) still.push_back(s);
       else if (t_stop[s] < 0.0) t_stop[s] = now;
+    }
+    if (ctx->progress_interval > 0.0 && now - last_print >= ctx->progress_interval) {
+      fprintf(stderr, "[ss_minimize_batch] step %lld: %zu of %d configurations running, t %.1fs\n",
+              (long long)tick, still.size(), count, now);
+      fflush(stderr);
+      last_print = now;
     }
     if (still.empty()) break;
     if (still.size() < active.size()) {

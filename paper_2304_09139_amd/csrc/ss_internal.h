@@ -107,6 +107,7 @@ struct ProfileLog {
     double work;  // pairs (n(k) and gradient passes) or table entries covered by the launch
   };
   int mask = 0;  // bit k: time kernel k
+  std::mutex mu;  // event records come from the caller's thread and the server's
   std::vector<Rec> ev[3];  // 0 n(k) pass, 1 gradient pass, 2 phase table
   std::vector<hipEvent_t> pool;
 };
@@ -132,8 +133,12 @@ struct ss_tile_entry {
   ss::TileSpec t;
 };
 
+struct ss_server;
+
 struct ss_ctx {
   int device = 0;
+  ss_server* server = nullptr;       // continuous-batching server, if started
+  double progress_interval = 0.0;    // > 0: quenches print progress lines to stderr this often (s)
   std::vector<ss_tile_entry> tiles;  // batched tile table, first match wins
   std::string last_error;
   std::mutex mu;

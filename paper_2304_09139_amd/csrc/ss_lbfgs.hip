@@ -30,6 +30,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <stdio.h>
+
 #include <chrono>
 #include <vector>
 
@@ -577,6 +579,24 @@ __global__ void __launch_bounds__(kThreads) k_dots_final(MinState* S_, MinParams
   dots_final_body(S_, P, mode, G, partial, eblk, neblk);
 }
 
+// progress record of a quench: running, iteration, evaluations, Phi.hi, S_max.hi
+struct Progress {
+  int32_t running, pad;
+  int64_t iter, evals;
+  double f, smax;
+};
+
+__global__ void k_progress(const MinState* S_, Progress* out) {
+  if (threadIdx.x != 0) return;
+  const MinState& S = *S_;
+  out->running = S.running;
+  out->pad = 0;
+  out->iter = S.iter;
+  out->evals = S.evals;
+  out->f = S.f[0];
+  out->smax = S.smax[0];
+}
+
 // x <- xt, g <- gt after an accepted trial
 __device__ __forceinline__ void accept_body(const VecSet& V, const MinState* S_, int64_t nv, int64_t bx) {
   if (!S_->accepted) return;
@@ -671,7 +691,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t lbfgs_bytes(int64_t nv) {
   const size_t vec = al256(sizeof(double) * 2 * (size_t)nv);
   return vec * (4 + 2 * (kMaxHistory + 1)) + al256(sizeof(MinState)) +
-         al256(sizeof(double) * 2 * kMaxDots * kDotBlocks) + 256;
+         al256(sizeof(double) * 2 * kMaxDots * kDotBlocks + 64) + 256;
 }
 
 struct Layout {
@@ -696,7 +716,7 @@ void carve(char* base, int64_t nv, double* x, Layout* L) {
   for (int i = 0; i <= kMaxHistory; ++i) L->V.S[i] = (double*)take(vec);
   for (int i = 0; i <= kMaxHistory; ++i) L->V.Y[i] = (double*)take(vec);
   L->state = (MinState*)take(al256(sizeof(MinState)));
-  L->partial = (double*)take(al256(sizeof(double) * 2 * kMaxDots * kDotBlocks));
+  L->partial = (double*)take(al256(sizeof(double) * 2 * kMaxDots * kDotBlocks + 64));
 }
 
 }  // namespace
@@ -789,9 +809,19 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
   // ticks, enqueued kDepth ahead; the status word of each tick is copied to
   // pinned memory and read once that tick's event has completed
   constexpr int kDepth = 3;
+  // per tick: the running word (and, with progress lines on, a Progress record)
+  const double progress = ctx->progress_interval;
+  Progress* prog_dev = (Progress*)(Lay.partial + 2 * kMaxDots * kDotBlocks);  // spare room of the dot partials
+  Progress* prog_host = nullptr;
   int32_t* flags = nullptr;
   hipEvent_t ev[kDepth] = {};
   if (!ok(hipHostMalloc((void**)&flags, sizeof(int32_t) * kDepth, hipHostMallocDefault), "hipHostMalloc")) return err;
+  if (progress > 0.0 &&
+      !ok(hipHostMalloc((void**)&prog_host, sizeof(Progress) * kDepth, hipHostMallocDefault), "hipHostMalloc")) {
+    hipHostFree(flags);
+    return err;
+  }
+  auto last_print = std::chrono::steady_clock::now();
   for (int q = 0; q < kDepth && err == SS_OK; ++q) ok(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "event");
 
   // one stage: a fresh start (history cleared) from the current positions
@@ -814,11 +844,28 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
       if (!ok(hipGetLastError(), "decision kernels")) break;
       const int q = (int)(tick % kDepth);
       if (!ok(hipMemcpyAsync(flags + q, running, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag copy")) break;
+      if (prog_host) {
+        hipLaunchKernelGGL(k_progress, dim3(1), dim3(64), 0, st, S, prog_dev);
+        if (!ok(hipMemcpyAsync(prog_host + q, prog_dev, sizeof(Progress), hipMemcpyDeviceToHost, st),
+                "progress copy"))
+          break;
+      }
       if (!ok(hipEventRecord(ev[q], st), "event record")) break;
       ++tick;
       if (tick >= kDepth) {
         const int w = (int)(tick % kDepth);  // the oldest tick in flight
         if (!ok(hipEventSynchronize(ev[w]), "event sync")) break;
+        if (prog_host) {
+          const auto now = std::chrono::steady_clock::now();
+          if (std::chrono::duration<double>(now - last_print).count() >= progress) {
+            const Progress& pr = prog_host[w];
+            fprintf(stderr, "[ss_minimize] %s iter %lld evals %lld Phi %.6e S_max %.6e t %.1fs\n",
+                    fp64 ? "fp64" : "dd", (long long)pr.iter, (long long)pr.evals, pr.f, pr.smax,
+                    std::chrono::duration<double>(now - t0).count());
+            fflush(stderr);
+            last_print = now;
+          }
+        }
         if (flags[w] == 0) break;
       }
     }
@@ -848,6 +895,7 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
   for (int q = 0; q < kDepth; ++q)
     if (ev[q]) hipEventDestroy(ev[q]);
   hipHostFree(flags);
+  if (prog_host) hipHostFree(prog_host);
   if (err != SS_OK) return err;
   out->status = hs.status;
   out->iters = iters;

@@ -74,3 +74,22 @@ def batch_shapes(count: int, seed: int = 3, n_min: int = 500, n_max: int = 5000,
         chi = chis[int(r[2] % np.uint64(len(chis)))]
         out.append((d, N, chi))
     return out
+
+
+def serve_stream(count: int, seed: int = 5, n_min: int = 500, n_max: int = 5000, dims=(2, 3),
+                 chi_min: float = 0.1, chi_max: float = 0.49) -> list[tuple[int, int, float, float]]:
+    """A seeded stream of quench requests (d, N, chi, t): d uniform over ``dims``,
+    N log-uniform on [n_min, n_max], chi uniform on [chi_min, chi_max], and
+    arrival times t of a unit-rate Poisson process (exponential gaps -ln(1 - U))."""
+    raw = splitmix64(stream_seed(seed, count), 4 * count).reshape(count, 4)
+    out = []
+    t = 0.0
+    lo, hi = np.log10(n_min), np.log10(n_max)
+    for r in raw:
+        u = [float(x >> np.uint64(11)) * 2.0 ** -53 for x in r[1:]]
+        d = dims[int(r[0] % np.uint64(len(dims)))]
+        N = int(round(10.0 ** (lo + (hi - lo) * u[0])))
+        chi = chi_min + (chi_max - chi_min) * u[1]
+        t += -np.log1p(-u[2])
+        out.append((d, N, chi, t))
+    return out

@@ -50,6 +50,11 @@ class Tile(ctypes.Structure):
                 ("nk_chunk", ctypes.c_int64), ("grad_k", ctypes.c_int64)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int64), ("R2", ctypes.c_int64), ("L", ctypes.c_double),
+                ("vkind", ctypes.c_int32), ("pos_host", ctypes.c_void_p), ("opts", MinOpts)]
+
+
 _V = ctypes.c_void_p
 _I64P = ctypes.POINTER(ctypes.c_int64)
 _SZP = ctypes.POINTER(ctypes.c_size_t)
@@ -69,6 +74,7 @@ SIGNATURES = {
                                       ctypes.c_size_t, _V]),
     "ss_energy_grad_fp64": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V, _V, _V, _V, _V, _V,
                                            ctypes.c_size_t, _V]),
+    "ss_set_progress": (ctypes.c_int, [_V, ctypes.c_double]),
     "ss_profile_enable": (ctypes.c_int, [_V, ctypes.c_int]),
     "ss_profile_read": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int, _I64P, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
@@ -81,6 +87,10 @@ SIGNATURES = {
     "ss_minimize_batch": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(_V),
                                          ctypes.POINTER(_V), ctypes.POINTER(MinOpts), ctypes.POINTER(MinResult),
                                          _V, ctypes.c_size_t, _V]),
+    "ss_server_start": (ctypes.c_int, [_V, _V, ctypes.c_size_t, ctypes.c_int]),
+    "ss_submit": (ctypes.c_int, [_V, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "ss_poll": (ctypes.c_int, [_V, ctypes.c_uint64, ctypes.POINTER(MinResult), _V]),
+    "ss_server_stop": (ctypes.c_int, [_V]),
 }
 
 DEFAULT_MIN_OPTS = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=50, stall_ratio=0.99, c1=1e-4,
@@ -139,6 +149,12 @@ def _stream(device):
 STATUS = {0: "converged", 1: "stalled", 2: "max_iter", 3: "numeric"}
 
 
+def _result(r) -> dict:
+    return dict(status=STATUS.get(r.status, str(r.status)), iters=r.iters, evals=r.evals, grad_evals=r.grad_evals,
+                phi=(r.phi[0], r.phi[1]), smax=(r.smax[0], r.smax[1]), seconds=r.seconds,
+                iters_fp64=r.iters_fp64)
+
+
 @dataclass
 class Workload:
     d: int
@@ -188,6 +204,10 @@ class Context:
 
     def _chk(self, rc, what):
         return _check(rc, self._h, what)
+
+    def progress(self, seconds: float) -> None:
+        """Print progress lines of long quenches to stderr at most every `seconds` (0: off)."""
+        self._chk(lib().ss_set_progress(self._h, seconds), "ss_set_progress")
 
     KERNELS = {"nk": 0, "grad": 1, "table": 2}
 
@@ -269,9 +289,7 @@ class Context:
         self._chk(lib().ss_minimize(self._h, ctypes.byref(p), _ptr(n), _ptr(v), _ptr(pos), ctypes.byref(mo),
                                     ctypes.byref(res), _ptr(ws), ws.numel(), _stream(self.device)),
                   "ss_minimize")
-        return dict(status=STATUS.get(res.status, str(res.status)), iters=res.iters, evals=res.evals,
-                    grad_evals=res.grad_evals, phi=(res.phi[0], res.phi[1]), smax=(res.smax[0], res.smax[1]),
-                    seconds=res.seconds, iters_fp64=res.iters_fp64)
+        return _result(res)
 
     # ---- batches ---------------------------------------------------------------
     def set_tiles(self, tiles: list[dict]) -> None:
@@ -328,6 +346,46 @@ class Context:
         res = (MinResult * n)()
         self._chk(lib().ss_minimize_batch(self._h, n, probs, v_arr, pos_arr, mos, res, _ptr(ws), ws.numel(),
                                           _stream(self.device)), "ss_minimize_batch")
-        return [dict(status=STATUS.get(r.status, str(r.status)), iters=r.iters, evals=r.evals,
-                     grad_evals=r.grad_evals, phi=(r.phi[0], r.phi[1]), smax=(r.smax[0], r.smax[1]),
-                     seconds=r.seconds, iters_fp64=r.iters_fp64) for r in res]
+        return [_result(r) for r in res]
+
+    # ---- serving -----------------------------------------------------------------
+    def server_start(self, arena_bytes: int, max_slots: int = 256) -> None:
+        """Start the continuous-batching server with a device arena of arena_bytes."""
+        self._arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize()
+        self._chk(lib().ss_server_start(self._h, _ptr(self._arena), arena_bytes, max_slots), "ss_server_start")
+
+    def submit(self, w: Workload, pos, **opts) -> int:
+        """Queue a quench of host positions pos (float64 [2, d, N]); returns its ticket."""
+        import numpy as np
+
+        o = dict(DEFAULT_MIN_OPTS)
+        o.update(opts)
+        p = np.ascontiguousarray(pos, dtype=np.float64)
+        if p.shape != (2, w.d, w.N):
+            raise ValueError("positions must be [2, d, N]")
+        req = Request(w.d, w.N, w.R2, w.L, w.vkind, p.ctypes.data, MinOpts(**o))
+        t = ctypes.c_uint64()
+        self._chk(lib().ss_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "ss_submit")
+        self._served = getattr(self, "_served", {})
+        self._served[t.value] = (w.d, w.N)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (result dict, final positions [2, d, N])."""
+        import numpy as np
+
+        d, N = self._served[ticket]
+        out = np.empty((2, d, N), dtype=np.float64)
+        res = MinResult()
+        rc = lib().ss_poll(self._h, ticket, ctypes.byref(res), out.ctypes.data_as(ctypes.c_void_p))
+        if rc == SS_PENDING:
+            return None
+        self._chk(rc, "ss_poll")
+        del self._served[ticket]
+        return _result(res), out
+
+    def server_stop(self) -> None:
+        rc = lib().ss_server_stop(self._h)
+        self._arena = None
+        self._chk(rc, "ss_server_stop")

@@ -1,0 +1,143 @@
+"""Serving (ss_server_start / ss_submit / ss_poll / ss_server_stop).
+
+A served request runs the batched minimiser under the same tile table, so its
+result must equal ss_minimize_batch's result for the same configuration bit for
+bit, whether it is served alone or mixed with other requests arriving at other
+times; served quenches reach the stated floor (re-evaluated by the oracle);
+admission waits for arena space; errors are reported per request.
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2304_09139_amd import inputs, ss
+
+pytestmark = pytest.mark.gpu
+
+FLOOR = 1e-40
+
+
+@pytest.fixture()
+def ctx():
+    c = ss.Context(0)
+    yield c
+    c.close()
+
+
+def wait(ctx, ticket, limit=120.0):
+    t0 = time.time()
+    while True:
+        r = ctx.poll(ticket)
+        if r is not None:
+            return r
+        assert time.time() - t0 < limit, f"ticket {ticket} still pending"
+        time.sleep(0.002)
+
+
+SPECS = [(2, 128, 0.4, 0, 1.0, 41), (3, 300, 0.3, 1, 1.0, 42), (2, 700, 0.35, 0, 2.0, 43),
+         (3, 500, 0.45, 0, 1.0, 44), (2, 96, 0.2, 0, 1.0, 45)]
+
+
+def make(spec):
+    d, N, chi, vkind, L, cid = spec
+    return ss.Workload.from_chi(d, N, chi, L=L, vkind=vkind), inputs.config_positions(cid, d, N, 0)
+
+
+def test_served_equals_batch_alone_and_mixed(ctx):
+    """Bitwise: batch of one == served alone == served in a staggered mix."""
+    items = [make(s) for s in SPECS]
+    opts = dict(max_iter=60, s_floor=0.0)
+    ref = []
+    for w, pos in items:
+        x = torch.from_numpy(pos).cuda()
+        v = ctx.weights(w, ctx.wavevectors(w.d, w.R2)) if w.vkind else None
+        r = ctx.minimize_batch([w], [x], [v], opts=opts)[0]
+        ref.append((r, x.cpu().numpy()))
+    ctx.server_start(1 << 30, max_slots=8)
+    try:
+        # alone
+        for (w, pos), (rb, xb) in zip(items, ref):
+            r, xs = wait(ctx, ctx.submit(w, pos, **opts))
+            assert np.array_equal(xs, xb) and r["phi"] == rb["phi"] and r["evals"] == rb["evals"]
+        # mixed: staggered submissions in another order
+        tickets = {}
+        for i in [3, 0, 4, 1, 2]:
+            tickets[i] = ctx.submit(items[i][0], items[i][1], **opts)
+            time.sleep(0.003)
+        for i, t in tickets.items():
+            r, xs = wait(ctx, t)
+            rb, xb = ref[i]
+            assert np.array_equal(xs, xb), SPECS[i]
+            assert r["phi"] == rb["phi"] and r["smax"] == rb["smax"] and r["iters"] == rb["iters"], SPECS[i]
+    finally:
+        ctx.server_stop()
+
+
+def test_served_quenches_reach_floor(ctx):
+    items = [make(s) for s in SPECS]
+    ctx.server_start(1 << 30, max_slots=3)   # fewer slots than requests: queueing
+    try:
+        tickets = [ctx.submit(w, pos, s_floor=FLOOR) for w, pos in items]
+        for (w, pos), t, spec in zip(items, tickets, SPECS):
+            r, xs = wait(ctx, t)
+            assert r["status"] == "converged", (spec, r)
+            n = O.wavevectors(w.d, w.R2)
+            v = O.weights(n, w.R2, 1) if w.vkind else None
+            e = O.energy_from_nk(w.N, v, O.nk(n, xs))
+            assert e.smax[0] <= FLOOR * (1 + 1e-6), (spec, e.smax, r["smax"])
+            print(f"{spec}: iters={r['iters']} latency={r['seconds']:.3f}s")
+    finally:
+        ctx.server_stop()
+
+
+def test_small_arena_admission(ctx):
+    """An arena that holds about one configuration at a time still serves all
+    requests, one after another; a request larger than the arena fails alone."""
+    items = [make(s) for s in SPECS[:3]]
+    need = max(ctx.batch_workspace_size([w], [dict(ss.DEFAULT_MIN_OPTS)]) for w, _ in items)
+    ctx.server_start(int(need * 1.5), max_slots=4)
+    try:
+        big = ss.Workload.from_chi(3, 6000, 0.45)
+        tb = ctx.submit(big, inputs.config_positions(46, 3, 6000, 0), max_iter=5)
+        tickets = [ctx.submit(w, pos, max_iter=40, s_floor=0.0) for w, pos in items]
+        for t in tickets:
+            r, _ = wait(ctx, t)
+            assert r["iters"] == 40
+        with pytest.raises(ss.SSError) as e:
+            wait(ctx, tb)
+        assert e.value.code == ss.SS_ENOMEM
+    finally:
+        ctx.server_stop()
+
+
+def test_serving_errors(ctx):
+    w, pos = make(SPECS[0])
+    with pytest.raises(ss.SSError) as e:
+        ctx.submit(w, pos)
+    assert e.value.code == ss.SS_ESTATE
+    ctx.server_start(1 << 28, max_slots=2)
+    try:
+        with pytest.raises(ss.SSError) as e:
+            ctx.server_start(1 << 20, max_slots=2)
+        assert e.value.code == ss.SS_ESTATE
+        for bad in (dict(history=0), dict(precision=2)):
+            with pytest.raises(ss.SSError) as e:
+                ctx.submit(w, pos, **bad)
+            assert e.value.code == ss.SS_EINVAL
+        badpos = pos.copy()
+        badpos[0, 0, 0] = np.inf
+        with pytest.raises(ss.SSError) as e:
+            ctx.submit(w, badpos)
+        assert e.value.code == ss.SS_EINVAL
+        assert ss.lib().ss_poll(ctx._h, 987654321, None, None) == ss.SS_ENOTFOUND
+        t = ctx.submit(w, pos, max_iter=0)
+        r, xs = wait(ctx, t)
+        assert r["iters"] == 0 and np.array_equal(xs, pos)
+        assert ss.lib().ss_poll(ctx._h, t, None, None) == ss.SS_ENOTFOUND
+    finally:
+        ctx.server_stop()
+    ctx.server_stop()  # stopping twice is harmless
