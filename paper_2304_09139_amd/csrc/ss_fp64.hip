@@ -191,7 +191,11 @@ __global__ void __launch_bounds__(kThreads) k_grad64(const Span* __restrict__ ru
                                                      const int* __restrict__ active) {
   if (active && *active == 0) return;
   __shared__ double s_g[kWaves][D][64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the wave index is uniform across the wave: in a scalar register the run
+  // bounds, the run records and the per-wavevector (vC, vS) become scalar loads
+  // and the wavevector loop is a scalar loop
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t j = (int64_t)blockIdx.x * 64 + lane;
   const int64_t jj = j < N ? j : N - 1;
   const int q = blockIdx.y;

@@ -309,7 +309,11 @@ __device__ __forceinline__ void grad_body(const Span* __restrict__ runs, const i
                                           int64_t N, int R1, int64_t M, double* __restrict__ gpart, int64_t pblock,
                                           int q) {
   __shared__ double s_g[kWaves][2 * D][64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the wave index is uniform across the wave: in a scalar register the run
+  // bounds, the run records and the per-wavevector (vC, vS) become scalar loads
+  // and the wavevector loop is a scalar loop
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t j = pblock * 64 + lane;
   const int64_t jj = j < N ? j : N - 1;
   const int r0 = chunk_begin[kWaves * q + wave], r1 = chunk_begin[kWaves * q + wave + 1];
@@ -326,6 +330,7 @@ __device__ __forceinline__ void grad_body(const Span* __restrict__ runs, const i
     double q0h = 0.0, q0l = 0.0, qdh = 0.0, qdl = 0.0;
     double nd = (double)run.n[D - 1];
     const double* cp = csw + run.k0;
+#pragma unroll 2
     for (int t = 0; t < run.len; ++t) {
       const double Ch = cp[t], Cl = cp[M + t], Sh = cp[2 * M + t], Sl = cp[3 * M + t];
       double qs, qt;
