@@ -116,6 +116,8 @@ def main():
                     help="seconds between the library's progress lines on stderr (0: none)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched workloads: skip timing the same configurations one at a time")
+    ap.add_argument("--method", default="lbfgs", choices=("lbfgs", "fire"),
+                    help="minimiser of the single-configuration quench")
     ap.add_argument("--precision", default="dd", choices=("dd", "staged", "fp64"),
                     help="evaluation precision of the quench (staged: FP64 until it stalls, then dd)")
     ap.add_argument("--evals", type=int, default=0,
@@ -146,7 +148,9 @@ def main():
     w = ss.Workload.from_chi(d, N, chi, vkind=vkind)
     n = ctx.wavevectors(d, w.R2)
     v = ctx.weights(w, n) if vkind else None
-    mopts = dict(s_floor=FLOOR, precision=args.precision)
+    mopts = dict(s_floor=FLOOR, precision=args.precision, method=args.method)
+    if args.method == "fire":
+        mopts["stall_window"] = 200
     # all starting configurations resident in HBM before the timed region
     starts = [torch.from_numpy(inputs.config_positions(wl["cfg_id"], d, N, r)).cuda()
               for r in range(args.warmup + args.steps)]
@@ -232,11 +236,12 @@ def main():
         "vs_baseline": None,
         "dtype": {"dd": "dd", "staged": "f64 then dd", "fp64": "f64"}[args.precision],
         "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
-        "config": {"workload": f"L-BFGS quench to S_max <= {FLOOR:g}, d={d}, N={N}, chi={chi}, "
+        "config": {"workload": f"{'FIRE' if args.method == 'fire' else 'L-BFGS'} quench to S_max <= {FLOOR:g}, "
+                               f"d={d}, N={N}, chi={chi}, "
                                + ("v(k)=(1-|k|/K)^2" if vkind else "v(k)=1")
                                + ("" if args.precision == "dd" else f", {args.precision} precision"),
                    "d": d, "N": N, "chi": chi, "R2": w.R2, "M": w.M, "s_floor": FLOOR, "vkind": vkind,
-                   "precision": args.precision, "parallelism": "single GPU"},
+                   "precision": args.precision, "method": args.method, "parallelism": "single GPU"},
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{args.steps}",
         "smax_worst": max(r["smax"][0] for r in results),

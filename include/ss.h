@@ -188,7 +188,16 @@ int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, doubl
  * re-evaluated, the stall window restarted and the kept (s, y) pairs carried
  * over (a steepest-descent restart with the capped step is far too long this
  * close to a minimum).  The minimiser's own vectors and dot products are
- * double-double in every mode. */
+ * double-double in every mode.
+ * Method 1 is FIRE, the paper's minimiser ("Simulations"; Bitzek, Koskinen,
+ * Gaehler, Moseler, Gumbsch, PRL 97, 170201 (2006)) with its published
+ * parameters: unit masses, F = -g; per step P = F.v; if P > 0 the velocity is
+ * mixed, v <- (1 - a) v + a |v| F/|F|, and after more than N_min = 5
+ * consecutive such steps dt <- min(1.1 dt, dt_max) and a <- 0.99 a; if P <= 0
+ * then dt <- dt / 2, v <- 0, a <- 0.1; then v <- v + dt F, x <- x + dt v.
+ * dt0^2 max|g(x0)| = step_cap N^(-1/d), dt_max = 10 dt0.  history, c1,
+ * max_halvings and max_ls_fail do not apply; the stopping rules are the same
+ * (FIRE's energy is not monotone, so a longer stall_window suits it). */
 typedef struct {
   int32_t history;      /* 1..16 (8 is typical)                 */
   int64_t max_iter;     /* >= 0                                 */
@@ -201,6 +210,7 @@ typedef struct {
   int32_t max_ls_fail;  /* >= 1                                 */
   int32_t precision;    /* 0 double-double, 1 FP64, 2 staged    */
   double fp64_floor;    /* >= 0: S_max floor of the FP64 stage  */
+  int32_t method;       /* 0 L-BFGS, 1 FIRE                     */
 } ss_min_opts;
 
 /* status: 0 converged (S_max <= s_floor), 1 stalled, 2 iteration cap,
@@ -266,7 +276,7 @@ int ss_batch_workspace_size(ss_ctx* ctx, int count, const ss_problem* probs, con
  * place; v_dev[i] is the weight table double[2][M_i] for vkind != 0 (v_dev may
  * be NULL when every vkind is 0).  The wavevector sets are built internally
  * from (d_i, R2_i).  ws: ss_batch_workspace_size bytes of device memory.
- * Batched quenches evaluate in double-double (precision must be 0).
+ * Batched quenches run L-BFGS in double-double (precision and method 0).
  * Synchronising: returns when every quench has stopped, with out[i] filled;
  * out[i].seconds is the time from the call until the library saw quench i
  * stop.  Returns SS_OK (individual non-finite energies show as status 3), or an
@@ -296,7 +306,7 @@ typedef struct {
   double L;                /* box side                                                 */
   int32_t vkind;           /* 0: v = 1; 1: v = (1 - |k|/K)^2, computed by the library   */
   const double* pos_host;  /* double[2][d][N] fractional starting positions (host)      */
-  ss_min_opts opts;        /* minimiser options; precision must be 0                   */
+  ss_min_opts opts;        /* minimiser options; precision and method must be 0        */
 } ss_request;
 
 /* Start the server.  arena_dev: caller-owned device memory that holds every

@@ -49,7 +49,7 @@ class LbfgsOpts(ctypes.Structure):
                 ("s_floor", ctypes.c_double), ("stall_window", ctypes.c_int),
                 ("stall_ratio", ctypes.c_double), ("c1", ctypes.c_double),
                 ("step_cap", ctypes.c_double), ("max_halvings", ctypes.c_int),
-                ("max_ls_fail", ctypes.c_int)]
+                ("max_ls_fail", ctypes.c_int), ("method", ctypes.c_int)]
 
 
 class LbfgsResult(ctypes.Structure):
@@ -260,19 +260,23 @@ def energy_grad(n, v, pos, L: float = 1.0, want_grad: bool = True):
 # --- minimiser ----------------------------------------------------------------
 
 DEFAULT_OPTS = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=50,
-                    stall_ratio=0.99, c1=1e-4, step_cap=1e-2, max_halvings=40, max_ls_fail=3)
+                    stall_ratio=0.99, c1=1e-4, step_cap=1e-2, max_halvings=40, max_ls_fail=3, method=0)
+METHODS = {"lbfgs": 0, "fire": 1}
 
-STATUS = {0: "converged", 1: "stalled", 2: "max_iter"}
+STATUS = {0: "converged", 1: "stalled", 2: "max_iter", 3: "numeric"}
 
 
 def _opts(**kw) -> LbfgsOpts:
     o = dict(DEFAULT_OPTS)
     o.update(kw)
+    if isinstance(o["method"], str):
+        o["method"] = METHODS[o["method"]]
     return LbfgsOpts(**o)
 
 
 def minimize(n, v, pos, L: float = 1.0, trace_cap: int = 0, **kw):
-    """L-BFGS on the stealthy energy; returns (pos_out, result dict, phi trace [k,2])."""
+    """L-BFGS (method="lbfgs") or FIRE (method="fire") on the stealthy energy;
+    returns (pos_out, result dict, phi trace [k,2])."""
     n = np.ascontiguousarray(n, dtype=np.int32)
     x = np.array(pos, dtype=np.float64, copy=True, order="C")
     M, d = n.shape

@@ -539,6 +539,7 @@ typedef struct {
     double step_cap;      /* first/reset step moves at most step_cap * N^(-1/d)   */
     int max_halvings;     /* line-search halvings before a failure is recorded    */
     int max_ls_fail;      /* consecutive failures that end the run as stalled     */
+    int method;           /* 0 L-BFGS, 1 FIRE                                     */
 } or_lbfgs_opts;
 
 typedef struct {
@@ -728,6 +729,94 @@ static int lbfgs_run(objective* o, int64_t nv, dd* x, const or_lbfgs_opts* op,
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* FIRE, the paper's minimiser ("Simulations"; Bitzek, Koskinen, Gaehler,      */
+/* Moseler and Gumbsch, Phys. Rev. Lett. 97, 170201 (2006)).  Unit masses,      */
+/* force F = -g.  Each iteration: P = F.v; the velocity is mixed towards the   */
+/* force direction, v <- (1 - a) v + a |v| F/|F|; if P > 0 the count of        */
+/* consecutive uphill-free steps grows and, once it exceeds N_min, the step    */
+/* grows (dt <- min(f_inc dt, dt_max)) and a shrinks (a <- f_a a); if P <= 0    */
+/* the step shrinks (dt <- f_dec dt), the system is frozen (v <- 0) and         */
+/* a <- a_start.  Then one semi-implicit Euler step: v <- v + dt F,             */
+/* x <- x + dt v, and a new evaluation.  The published parameters are used:    */
+/* N_min 5, f_inc 1.1, f_dec 0.5, a_start 0.1, f_a 0.99, dt_max = 10 dt0;       */
+/* dt0^2 max|g(x0)| = step_cap N^(-1/d).  The stopping rules are the L-BFGS     */
+/* ones (floor, stall window, cap).                                             */
+/* ------------------------------------------------------------------------- */
+static int fire_run(objective* o, int64_t nv, dd* x, const or_lbfgs_opts* op,
+                    or_lbfgs_result* res, double* phi_trace, int64_t trace_cap) {
+    const int n_min = 5;
+    const double f_inc = 1.1, f_dec = 0.5, a_start = 0.1, f_a = 0.99;
+    dd* g = (dd*)calloc((size_t)nv, sizeof(dd));
+    dd* v = (dd*)calloc((size_t)nv, sizeof(dd));
+    dd* fhist = (dd*)calloc((size_t)(op->max_iter + 2), sizeof(dd));
+    if (!g || !v || !fhist) return -1;
+    double nmean = pow((double)o->N, -1.0 / (double)(o->d > 0 ? o->d : 1));
+    if (o->kind == 1) nmean = 1.0;
+    const int64_t W = op->stall_window;
+    dd f, smax;
+    obj_eval(o, nv, x, &f, &smax, g);
+    res->evals = 1; res->grad_evals = 1;
+    /* initial step from the largest gradient component (compared in dd) */
+    dd gmax = dd_from(0.0);
+    for (int64_t i = 0; i < nv; i++) {
+        dd ag = g[i].hi < 0.0 ? dd_neg(g[i]) : g[i];
+        if (dd_gt(ag, gmax)) gmax = ag;
+    }
+    double dt = gmax.hi > 0.0 ? sqrt(op->step_cap * nmean / gmax.hi) : 0.0;
+    const double dt_max = 10.0 * dt;
+    double a = a_start;
+    int npos = 0;
+    int64_t it = 0;
+    int status = 2;
+    for (;;) {
+        if (phi_trace && it < trace_cap) { phi_trace[2 * it] = f.hi; phi_trace[2 * it + 1] = f.lo; }
+        fhist[it] = f;
+        if (!dd_gt(smax, dd_from(op->s_floor))) { status = 0; break; }
+        if (it >= op->max_iter) { status = 2; break; }
+        if (it >= 2 * W) {
+            dd recent = fhist[it], older = fhist[it - W];
+            for (int64_t i = it - W + 1; i <= it; i++) if (dd_lt(fhist[i], recent)) recent = fhist[i];
+            for (int64_t i = it - 2 * W + 1; i <= it - W; i++) if (dd_lt(fhist[i], older)) older = fhist[i];
+            if (dd_gt(recent, dd_mul_d(older, op->stall_ratio))) { status = 1; break; }
+        }
+        if (dt == 0.0) { status = 0; break; }  /* g = 0 at the start: a stationary point */
+        /* P = F.v = -(g.v) */
+        dd P = dd_neg(vdot(nv, g, v));
+        if (dd_gt(P, dd_from(0.0))) {
+            dd vn = dd_sqrt(vdot(nv, v, v));
+            dd gn = dd_sqrt(vdot(nv, g, g));
+            dd cg = dd_mul_d(dd_div(vn, gn), a);          /* a |v| / |F| */
+            dd cv = dd_from(1.0 - a);
+            for (int64_t i = 0; i < nv; i++) v[i] = dd_sub(dd_mul(cv, v[i]), dd_mul(cg, g[i]));
+            npos++;
+            if (npos > n_min) {
+                dt = fmin(dt * f_inc, dt_max);
+                a = a * f_a;
+            }
+        } else {
+            dt = dt * f_dec;
+            for (int64_t i = 0; i < nv; i++) v[i] = dd_from(0.0);
+            a = a_start;
+            npos = 0;
+        }
+        for (int64_t i = 0; i < nv; i++) {
+            v[i] = dd_sub(v[i], dd_mul_d(g[i], dt));
+            x[i] = dd_add(x[i], dd_mul_d(v[i], dt));
+        }
+        obj_eval(o, nv, x, &f, &smax, g);
+        res->evals++; res->grad_evals++;
+        it++;
+        if (!(f.hi == f.hi) || f.hi > 1e300) { status = 3; break; }
+    }
+    res->status = status;
+    res->iters = it;
+    res->phi[0] = f.hi; res->phi[1] = f.lo;
+    res->smax[0] = smax.hi; res->smax[1] = smax.lo;
+    free(g); free(v); free(fhist);
+    return 0;
+}
+
 /* Minimise the stealthy energy from the positions in pos ([2][d][N],
  * fractional, updated in place; not wrapped into the unit cell). */
 int or_minimize(int d, int64_t N, int64_t M, double L, const int32_t* n, const double* v,
@@ -742,7 +831,8 @@ int or_minimize(int d, int64_t N, int64_t M, double L, const int32_t* n, const d
     dd* x = (dd*)malloc(sizeof(dd) * (size_t)nv);
     if (!o.nk || !o.pos || !x) return -1;
     for (int64_t i = 0; i < nv; i++) { x[i].hi = pos[i]; x[i].lo = pos[nv + i]; }
-    int rc = lbfgs_run(&o, nv, x, op, res, phi_trace, trace_cap);
+    int rc = op->method == 1 ? fire_run(&o, nv, x, op, res, phi_trace, trace_cap)
+                             : lbfgs_run(&o, nv, x, op, res, phi_trace, trace_cap);
     for (int64_t i = 0; i < nv; i++) { pos[i] = x[i].hi; pos[nv + i] = x[i].lo; }
     free(o.nk); free(o.pos); free(x);
     return rc;
@@ -758,7 +848,8 @@ int or_minimize_quadratic(int64_t nv, const double* w, const double* c, double* 
     dd* x = (dd*)malloc(sizeof(dd) * (size_t)nv);
     if (!x) return -1;
     for (int64_t i = 0; i < nv; i++) { x[i].hi = x_io[i]; x[i].lo = x_io[nv + i]; }
-    int rc = lbfgs_run(&o, nv, x, op, res, phi_trace, trace_cap);
+    int rc = op->method == 1 ? fire_run(&o, nv, x, op, res, phi_trace, trace_cap)
+                             : lbfgs_run(&o, nv, x, op, res, phi_trace, trace_cap);
     for (int64_t i = 0; i < nv; i++) { x_io[i] = x[i].hi; x_io[nv + i] = x[i].lo; }
     free(x);
     return rc;

@@ -52,8 +52,8 @@ int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot
     ctx->last_error = "invalid minimiser options";
     return SS_EINVAL;
   }
-  if (op->precision != 0) {
-    ctx->last_error = "batched quenches evaluate in double-double only (precision 0)";
+  if (op->precision != 0 || op->method != 0) {
+    ctx->last_error = "batched quenches run L-BFGS in double-double only (precision 0, method 0)";
     return SS_EINVAL;
   }
   h->prob = *p;

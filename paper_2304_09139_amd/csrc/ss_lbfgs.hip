@@ -579,6 +579,182 @@ __global__ void __launch_bounds__(kThreads) k_dots_final(MinState* S_, MinParams
   dots_final_body(S_, P, mode, G, partial, eblk, neblk);
 }
 
+// ---------------------------------------------------------------------------
+// FIRE (the paper's minimiser; Bitzek et al., PRL 97, 170201 (2006)), unit
+// masses, F = -g, velocities in V.p.  One step: P = F.v; if P > 0 the velocity
+// is mixed, v <- (1 - a) v + a |v| F / |F|, and after more than N_min = 5
+// consecutive such steps dt <- min(1.1 dt, dt_max), a <- 0.99 a; otherwise
+// dt <- dt / 2, v <- 0, a <- 0.1; then v <- v + dt F, x <- x + dt v and the
+// energy and gradient at the new x.  dt0^2 max|g(x0)| = step_cap N^(-1/d) and
+// dt_max = 10 dt0 are set by the host; dt and a are IEEE doubles.
+// ---------------------------------------------------------------------------
+constexpr int kFireDots = 3;  // g.v, g.g, v.v
+
+__device__ __forceinline__ void fire_dots_body(const VecSet& V, const MinState* S_, int64_t nv,
+                                               double* __restrict__ partial, int bx, int q, int G) {
+  if (!S_->running) return;
+  __shared__ double s_h[kThreads / 64], s_l[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t per = (nv + G - 1) / G;
+  const int64_t i0 = (int64_t)bx * per;
+  const int64_t i1 = i0 + per < nv ? i0 + per : nv;
+  const double* a = q == 2 ? V.p : V.g;
+  const double* b = q == 1 ? V.g : V.p;
+  dd acc{0.0, 0.0};
+  for (int64_t i = i0 + tid; i < i1; i += kThreads) acc = dd_add(acc, dd_mul(vload(a, nv, i), vload(b, nv, i)));
+  for (int m = 32; m > 0; m >>= 1) acc = dd_add(acc, shfl_xor_dd(acc, m));
+  if (lane == 0) {
+    s_h[wave] = acc.h;
+    s_l[wave] = acc.l;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    dd r{s_h[0], s_l[0]};
+    for (int w = 1; w < kThreads / 64; ++w) r = dd_add(r, dd{s_h[w], s_l[w]});
+    partial[((int64_t)q * G + bx) * 2] = r.h;
+    partial[((int64_t)q * G + bx) * 2 + 1] = r.l;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_fire_dots(VecSet V, const MinState* S_, int64_t nv,
+                                                        double* __restrict__ partial) {
+  fire_dots_body(V, S_, nv, partial, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// one block: the three products in range order, then the FIRE decisions
+__global__ void __launch_bounds__(kThreads) k_fire_final(MinState* S_, int G, const double* __restrict__ partial) {
+  MinState& S = *S_;
+  if (!S.running) return;
+  const int tid = threadIdx.x;
+  if (tid >= 64) return;
+  __shared__ double s_d[kFireDots][2];
+  if (tid < kFireDots) {
+    dd r{0.0, 0.0};
+    for (int b = 0; b < G; ++b) r = dd_add(r, dd{partial[((int64_t)tid * G + b) * 2], partial[((int64_t)tid * G + b) * 2 + 1]});
+    s_d[tid][0] = r.h;
+    s_d[tid][1] = r.l;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  if (S.fdt == 0.0) {  // g = 0 at the start: a stationary point
+    S.status = 0;
+    S.running = 0;
+    return;
+  }
+  const dd gv{s_d[0][0], s_d[0][1]}, gg{s_d[1][0], s_d[1][1]}, vv{s_d[2][0], s_d[2][1]};
+  const dd P = dd_neg(gv);
+  if (P.h > 0.0 || (P.h == 0.0 && P.l > 0.0)) {
+    const double a = S.fa;
+    const dd cg = dd_mul_d(dd_div(dd_sqrt(vv), dd_sqrt(gg)), a);
+    st(S.fcv, dd{1.0 - a, 0.0});
+    st(S.fcg, cg);
+    S.fire_reset = 0;
+    S.npos += 1;
+    if (S.npos > 5) {
+      const double up = S.fdt * 1.1;
+      S.fdt = up < S.fdt_max ? up : S.fdt_max;
+      S.fa = a * 0.99;
+    }
+  } else {
+    S.fdt = S.fdt * 0.5;
+    S.fire_reset = 1;
+    S.fa = 0.1;
+    S.npos = 0;
+  }
+}
+
+// v <- mix(v, g); v <- v - dt g; x <- x + dt v
+__global__ void __launch_bounds__(kThreads) k_fire_step(VecSet V, const MinState* S_, int64_t nv) {
+  const MinState& S = *S_;
+  if (!S.running) return;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= nv) return;
+  const double dt = S.fdt;
+  const dd g = vload(V.g, nv, i);
+  dd v{0.0, 0.0};
+  if (!S.fire_reset) v = dd_sub(dd_mul(ld(S.fcv), vload(V.p, nv, i)), dd_mul(ld(S.fcg), g));
+  v = dd_sub(v, dd_mul_d(g, dt));
+  const dd x = dd_add(vload(V.x, nv, i), dd_mul_d(v, dt));
+  V.p[i] = v.h;
+  V.p[nv + i] = v.l;
+  V.x[i] = x.h;
+  V.x[nv + i] = x.l;
+}
+
+// after the evaluation at the new x: Phi and S_max from the energy pass's block
+// partials, the finite check and the start-of-iteration tests
+__global__ void __launch_bounds__(kThreads) k_fire_top(MinState* S_, MinParams P, const double* __restrict__ eblk,
+                                                       int64_t neblk) {
+  MinState& S = *S_;
+  if (!S.running) return;
+  dd phi, sm;
+  double kk;
+  reduce_energy_partials(eblk, neblk, &phi, &sm, &kk);
+  const int tid = threadIdx.x;
+  if (tid >= 64) return;
+  const int64_t it = S.iter + 1;
+  if (tid == 0) {
+    S.iter = it;
+    S.evals += 1;
+    st(S.f, phi);
+    st(S.smax, sm);
+  }
+  if (!isfinite(phi.h)) {
+    if (tid == 0) {
+      S.status = 3;
+      S.running = 0;
+    }
+    return;
+  }
+  top_of_iteration(S, P, tid, it, phi, sm);
+}
+
+// FIRE start: dt0 from the host, v = 0, a = 0.1
+__global__ void __launch_bounds__(kThreads) k_fire_init(VecSet V, MinState* S_, int64_t nv, double dt0) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < nv) {
+    V.p[i] = 0.0;
+    V.p[nv + i] = 0.0;
+  }
+  if (i == 0) {
+    MinState& S = *S_;
+    S.fdt = dt0;
+    S.fdt_max = 10.0 * dt0;
+    S.fa = 0.1;
+    S.npos = 0;
+    S.fire_reset = 0;
+  }
+}
+
+// max |g_i| over the vector (one block, fixed order) for the initial step
+__global__ void __launch_bounds__(kThreads) k_gmax(const double* __restrict__ g, int64_t nv, double* __restrict__ out) {
+  __shared__ double s_h[kThreads], s_l[kThreads];
+  const int tid = threadIdx.x;
+  dd m{0.0, 0.0};
+  for (int64_t i = tid; i < nv; i += kThreads) {
+    dd x = vload(g, nv, i);
+    if (x.h < 0.0) x = dd_neg(x);
+    if (dd_less(m, x)) m = x;
+  }
+  s_h[tid] = m.h;
+  s_l[tid] = m.l;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      const dd a{s_h[tid], s_l[tid]}, b{s_h[tid + w], s_l[tid + w]};
+      if (dd_less(a, b)) {
+        s_h[tid] = b.h;
+        s_l[tid] = b.l;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = s_h[0];
+    out[1] = s_l[0];
+  }
+}
+
 // progress record of a quench: running, iteration, evaluations, Phi.hi, S_max.hi
 struct Progress {
   int32_t running, pad;
@@ -727,7 +903,7 @@ bool min_opts_valid(const ss_min_opts* op) {
   return op && op->history >= 1 && op->history <= kMaxHistory && op->max_iter >= 0 && op->stall_window >= 1 &&
          op->stall_window <= kMaxWindow && op->max_halvings >= 0 && op->max_ls_fail >= 1 && op->step_cap > 0.0 &&
          op->c1 > 0.0 && op->c1 < 1.0 && op->stall_ratio > 0.0 && op->precision >= 0 && op->precision <= 2 &&
-         op->fp64_floor >= 0.0;
+         op->fp64_floor >= 0.0 && op->method >= 0 && op->method <= 1;
 }
 
 MinParams min_params(const ss_min_opts* op, const ss_problem* prob) {
@@ -825,12 +1001,34 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
   for (int q = 0; q < kDepth && err == SS_OK; ++q) ok(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "event");
 
   // one stage: a fresh start (history cleared) from the current positions
+  const bool fire = op->method == 1;
   auto run_stage = [&](const MinParams& P, int keep) {
     if (!eval(pos_dev, S->f, S->smax, V.g, nullptr)) return;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, S, P, keep);
     ok(hipGetLastError(), "k_init");
+    if (fire) {  // the initial step from max|g(x0)| (one read-back)
+      double* gm = Lay.partial;
+      hipLaunchKernelGGL(k_gmax, dim3(1), dim3(kThreads), 0, st, V.g, nv, gm);
+      double hg[2] = {0.0, 0.0};
+      if (!ok(hipMemcpyAsync(hg, gm, sizeof(hg), hipMemcpyDeviceToHost, st), "gmax copy") ||
+          !ok(hipStreamSynchronize(st), "gmax sync"))
+        return;
+      const double dt0 = hg[0] > 0.0 ? sqrt(P.step / hg[0]) : 0.0;
+      hipLaunchKernelGGL(k_fire_init, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv, dt0);
+      ok(hipGetLastError(), "k_fire_init");
+    }
     int64_t tick = 0;
     while (err == SS_OK) {
+      if (fire) {
+        hipLaunchKernelGGL(k_fire_dots, dim3(dot_blocks, kFireDots), dim3(kThreads), 0, st, V, S, nv, Lay.partial);
+        hipLaunchKernelGGL(k_fire_final, dim3(1), dim3(64), 0, st, S, dot_blocks, Lay.partial);
+        hipLaunchKernelGGL(k_fire_step, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
+        if (!ok(hipGetLastError(), "FIRE step kernels")) break;
+        if (!eval(V.x, nullptr, nullptr, V.g, running)) break;
+        hipLaunchKernelGGL(k_fire_top, dim3(1), dim3(kThreads), 0, st, S, P, (const double*)(ews + c.off_blk),
+                           c.combine_blocks);
+        if (!ok(hipGetLastError(), "FIRE tests")) break;
+      } else {
       hipLaunchKernelGGL(k_dots, dim3(dot_blocks, 2 * P.m + 2), dim3(kThreads), 0, st, V, S, 0, nv, Lay.partial);
       hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kThreads), 0, st, S, P, 0, dot_blocks, Lay.partial, nullptr,
                          (int64_t)0);
@@ -842,6 +1040,7 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
                          (const double*)(ews + c.off_blk), c.combine_blocks);
       hipLaunchKernelGGL(k_accept, dim3(blocks_nv), dim3(kThreads), 0, st, V, S, nv);
       if (!ok(hipGetLastError(), "decision kernels")) break;
+      }
       const int q = (int)(tick % kDepth);
       if (!ok(hipMemcpyAsync(flags + q, running, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag copy")) break;
       if (prog_host) {

@@ -34,6 +34,10 @@ struct MinState {
   double dir_dots[kMaxDots][2];    // s_i.g (k), y_i.g (k), g.g, max|g|
   double trial_dots[kMaxDots][2];  // s.y, y.y, s_i.y (k), y.y_i (k) of the fresh pair
   double fhist[2 * kMaxWindow][2];
+  // FIRE (method 1): time step, its cap, the mixing parameter, consecutive P > 0 steps
+  double fdt, fdt_max, fa;
+  int32_t npos, fire_reset;
+  double fcv[2], fcg[2];  // this step's velocity mixing coefficients
 };
 
 struct MinParams {

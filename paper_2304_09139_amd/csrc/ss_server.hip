@@ -451,8 +451,8 @@ int check_request(ss_ctx* ctx, const ss_request* q, ss_problem* p) {
     ctx->last_error = "served requests take vkind 0 or 1";
     return SS_EINVAL;
   }
-  if (!min_opts_valid(&q->opts) || q->opts.precision != 0) {
-    ctx->last_error = "invalid minimiser options (served quenches use precision 0)";
+  if (!min_opts_valid(&q->opts) || q->opts.precision != 0 || q->opts.method != 0) {
+    ctx->last_error = "invalid minimiser options (served quenches use precision 0, method 0)";
     return SS_EINVAL;
   }
   if (!(q->L > 0.0) || !isfinite(q->L)) {

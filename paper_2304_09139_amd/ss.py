@@ -36,7 +36,8 @@ class MinOpts(ctypes.Structure):
     _fields_ = [("history", ctypes.c_int32), ("max_iter", ctypes.c_int64), ("s_floor", ctypes.c_double),
                 ("stall_window", ctypes.c_int32), ("stall_ratio", ctypes.c_double), ("c1", ctypes.c_double),
                 ("step_cap", ctypes.c_double), ("max_halvings", ctypes.c_int32),
-                ("max_ls_fail", ctypes.c_int32), ("precision", ctypes.c_int32), ("fp64_floor", ctypes.c_double)]
+                ("max_ls_fail", ctypes.c_int32), ("precision", ctypes.c_int32), ("fp64_floor", ctypes.c_double),
+                ("method", ctypes.c_int32)]
 
 
 class MinResult(ctypes.Structure):
@@ -94,8 +95,9 @@ SIGNATURES = {
 }
 
 DEFAULT_MIN_OPTS = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=50, stall_ratio=0.99, c1=1e-4,
-                        step_cap=1e-2, max_halvings=40, max_ls_fail=3, precision=0, fp64_floor=1e-26)
+                        step_cap=1e-2, max_halvings=40, max_ls_fail=3, precision=0, fp64_floor=1e-26, method=0)
 PRECISION = {"dd": 0, "fp64": 1, "staged": 2}
+METHOD = {"lbfgs": 0, "fire": 1}
 
 
 def lib():
@@ -282,6 +284,8 @@ class Context:
         base.update(opts)
         if isinstance(base["precision"], str):
             base["precision"] = PRECISION[base["precision"]]
+        if isinstance(base["method"], str):
+            base["method"] = METHOD[base["method"]]
         mo = MinOpts(**base)
         res = MinResult()
         ws = self.workspace(w, 1)

@@ -178,6 +178,51 @@ def lbfgs_mp(fg, x0, nmean, max_iter, history=8, c1=1e-4, step_cap=1e-2, max_hal
     return x, trace
 
 
+def fire_mp(fg, x0, nmean, max_iter, step_cap=1e-2):
+    """FIRE (Bitzek et al. 2006) for ``max_iter`` iterations at 256 bits.
+
+    Unit masses, F = -g.  Per iteration: P = F.v; if P > 0, v <- (1 - a) v +
+    a |v| F/|F|, the count of consecutive P > 0 steps grows and beyond 5 the step
+    grows (dt <- min(1.1 dt, dt_max)) and a <- 0.99 a; otherwise dt <- dt / 2,
+    v <- 0, a <- 0.1 and the count restarts; then v <- v + dt F, x <- x + dt v.
+    dt0 = sqrt(step_cap nmean / max|g(x0)|), dt_max = 10 dt0.  The step length
+    and a are IEEE doubles (as the minimiser keeps them); vectors are 256-bit.
+    Returns (x, list of f at each iterate).
+    """
+    x = list(x0)
+    f, g = fg(x)
+    v = [ctx.mpf(0)] * len(x)
+    gmax = float(max(abs(gi) for gi in g))
+    dt = math.sqrt(step_cap * nmean / gmax)
+    dt_max = 10.0 * dt
+    a = 0.1
+    npos = 0
+    trace = [f]
+    for _ in range(max_iter):
+        P = -sum(gi * vi for gi, vi in zip(g, v))
+        if P > 0:
+            vn = ctx.sqrt(sum(vi * vi for vi in v))
+            gn = ctx.sqrt(sum(gi * gi for gi in g))
+            cg = vn / gn * ctx.mpf(a)
+            cv = ctx.mpf(1.0 - a)
+            v = [cv * vi - cg * gi for vi, gi in zip(v, g)]
+            npos += 1
+            if npos > 5:
+                dt = min(dt * 1.1, dt_max)
+                a = a * 0.99
+        else:
+            dt = dt * 0.5
+            v = [ctx.mpf(0)] * len(x)
+            a = 0.1
+            npos = 0
+        mdt = ctx.mpf(dt)
+        v = [vi - mdt * gi for vi, gi in zip(v, g)]
+        x = [xi + mdt * vi for xi, vi in zip(x, v)]
+        f, g = fg(x)
+        trace.append(f)
+    return x, trace
+
+
 def quadratic_fg(w, c):
     """f = 1/2 sum w_i (x_i - c_i)^2 with mp vectors w, c."""
     def fg(x, want_grad=True):
