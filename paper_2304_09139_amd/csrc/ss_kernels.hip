@@ -88,6 +88,29 @@ __device__ __forceinline__ cdd lds_entry(const double* tp, int R1, int a, int m)
 // every staged particle.
 // part[((row * 4) + c) * M + k], c = (C.hi, C.lo, S.hi, S.lo), k in walk order.
 // ---------------------------------------------------------------------------
+// the staged particles of one tile for a wave whose longest piece has L
+// wavevectors: every lane walks L steps (lanes with shorter pieces compute terms
+// they never store), fully unrolled with no per-lane branches
+template <int D, int L>
+__device__ __forceinline__ void nk_tile(const double* __restrict__ lds, int np, int epp, int R1, const Span& sg,
+                                        double (&crh)[kSegLen], double (&crl)[kSegLen], double (&cih)[kSegLen],
+                                        double (&cil)[kSegLen]) {
+#pragma unroll 1
+  for (int p = 0; p < np; ++p) {
+    const double* tp = lds + p * epp;
+    cdd w = lds_entry(tp, R1, D - 1, sg.n[D - 1]);
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) w = cmul(w, lds_entry(tp, R1, a, sg.n[a]));
+    const cdd z = lds_entry(tp, R1, D - 1, 1);
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      lazy_acc(crh[t], crl[t], w.rh, w.rl);
+      lazy_acc(cih[t], cil[t], w.ih, w.il);
+      if (t + 1 < L) w = cmul(w, z);
+    }
+  }
+}
+
 template <int D, int PT>
 __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t nseg, const NkUnit u,
                                         const double* __restrict__ tab, int64_t N, int R1,
@@ -103,6 +126,9 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) crh[t] = crl[t] = cih[t] = cil[t] = 0.0;
 
+  // pieces are sorted longest first, so lane 0 of each wave holds the wave's
+  // longest piece: its length, in a scalar register, selects the unrolled walk
+  const int wl = __builtin_amdgcn_readfirstlane(len);
   const int64_t j0 = u.j0;
   const int64_t j1 = u.j1;
   for (int64_t tile = j0; tile < j1; tile += PT) {
@@ -114,27 +140,21 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
       lds[p * epp + ec] = p < np ? tab[(int64_t)ec * N + tile + p] : 0.0;
     }
     __syncthreads();
-    if (len > 0) {
-      for (int p = 0; p < np; ++p) {
-        const double* tp = lds + p * epp;
-        cdd w = lds_entry(tp, R1, D - 1, sg.n[D - 1]);
+    switch (wl) {
+      case 8: nk_tile<D, 8>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      case 7: nk_tile<D, 7>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      case 6: nk_tile<D, 6>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      case 5: nk_tile<D, 5>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      case 4: nk_tile<D, 4>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      case 3: nk_tile<D, 3>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      case 2: nk_tile<D, 2>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      case 1: nk_tile<D, 1>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      default: break;
+    }
 #pragma unroll
-        for (int a = 0; a < D - 1; ++a) w = cmul(w, lds_entry(tp, R1, a, sg.n[a]));
-        const cdd z = lds_entry(tp, R1, D - 1, 1);
-#pragma unroll
-        for (int t = 0; t < kSegLen; ++t) {
-          if (t < len) {
-            lazy_acc(crh[t], crl[t], w.rh, w.rl);
-            lazy_acc(cih[t], cil[t], w.ih, w.il);
-            if (t + 1 < len) w = cmul(w, z);
-          }
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < kSegLen; ++t) {
-        renorm(crh[t], crl[t]);
-        renorm(cih[t], cil[t]);
-      }
+    for (int t = 0; t < kSegLen; ++t) {
+      renorm(crh[t], crl[t]);
+      renorm(cih[t], cil[t]);
     }
   }
   // slot order: for each t the lanes of a wave write consecutive slots
@@ -152,7 +172,7 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
 }
 
 template <int D, int PT>
-__global__ void __launch_bounds__(kThreads) k_nk(const Span* __restrict__ segs, int64_t nseg,
+__global__ void __launch_bounds__(kThreads, 3) k_nk(const Span* __restrict__ segs, int64_t nseg,
                                                  const NkUnit* __restrict__ units, const double* __restrict__ tab,
                                                  int64_t N, int R1, double* __restrict__ part, int64_t M,
                                                  const SlotOffsets so, const int* __restrict__ active) {
@@ -381,10 +401,19 @@ template <int D>
 __global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs,
                                                    const int32_t* __restrict__ chunk_begin,
                                                    const double* __restrict__ tab, const double* __restrict__ csw,
-                                                   int64_t N, int R1, int64_t M, double* __restrict__ gpart,
+                                                   int64_t N, int R1, int64_t M, double* __restrict__ gpart, int Q,
                                                    const int* __restrict__ active) {
   if (active && *active == 0) return;
-  grad_body<D>(runs, chunk_begin, tab, csw, N, R1, M, gpart, blockIdx.x, blockIdx.y);
+  // XCD-aware order: workgroups go to the 8 XCDs round-robin by linear index,
+  // so block b runs on XCD b % 8; it takes particle block 8 k' + (b % 8) with
+  // k = b / 8 = k' Q + q, i.e. every chunk q of one particle block runs on the
+  // same XCD and the particle tables are fetched into one L2 only
+  const int64_t b = blockIdx.x;
+  const int64_t k = b / kXcds;
+  const int64_t pblock = (k / Q) * kXcds + (b % kXcds);
+  const int q = (int)(k % Q);
+  if (pblock * 64 >= N) return;
+  grad_body<D>(runs, chunk_begin, tab, csw, N, R1, M, gpart, pblock, q);
 }
 
 // sum the Q gradient partials (fixed order) and scale by 4 pi / L:
@@ -673,9 +702,10 @@ hipError_t launch_final(const LaunchCfg& c, const double* blk, double* phi, doub
 template <int D>
 static hipError_t launch_grad_d(const LaunchCfg& c, const Span* runs, const int32_t* chunk_begin, const double* tab,
                                 const double* csw, double* gpart, hipStream_t st, const int* active) {
-  const int64_t blocks = (c.N + 63) / 64;
-  hipLaunchKernelGGL((k_grad<D>), dim3((unsigned)blocks, (unsigned)c.Q), dim3(kThreads), 0, st, runs, chunk_begin,
-                     tab, csw, c.N, c.R1, c.M, gpart, active);
+  // particle blocks padded to a multiple of the XCD count (the padding exits)
+  const int64_t pblocks = ((c.N + 63) / 64 + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL((k_grad<D>), dim3((unsigned)(pblocks * c.Q)), dim3(kThreads), 0, st, runs, chunk_begin, tab,
+                     csw, c.N, c.R1, c.M, gpart, c.Q, active);
   return hipGetLastError();
 }
 
