@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="d3_N8000_chi0.45", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--progress", type=float, default=30.0,
+    ap.add_argument("--progress", type=float, default=0.0,
                     help="seconds between the library's progress lines on stderr (0: none)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched workloads: skip timing the same configurations one at a time")
@@ -210,7 +210,8 @@ def main():
     ctx.profile(False)
 
     evals = sum(r["evals"] for r in results)
-    pairs = w.M * N * evals
+    evals_fp64 = sum(r["evals_fp64"] for r in results)
+    pairs = w.M * N * (evals - evals_fp64)   # double-double pairs (the metric)
     value = pairs / elapsed
     converged = sum(1 for r in results if r["status"] == "converged")
     launches, ms = prof["grad"]
@@ -247,6 +248,8 @@ def main():
         "smax_worst": max(r["smax"][0] for r in results),
         "iters_mean": sum(r["iters"] for r in results) / len(results),
         "iters_fp64_mean": sum(r["iters_fp64"] for r in results) / len(results),
+        "evals_fp64_mean": evals_fp64 / len(results),
+        "fp64_pairs_per_s": w.M * N * evals_fp64 / elapsed,
         "evals_mean": evals / len(results),
         "eval_ms_nk_pass": nk_ms / max(nk_l, 1),
         "eval_ms_grad_pass": ms / max(launches, 1),

@@ -183,7 +183,9 @@ int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, doubl
  * FP64, "Simulations"): 0 evaluates every energy and gradient in double-double;
  * 1 in plain FP64 (the same sums with FP64 products and additions; S_max below
  * about 1e-25 is then rounding noise); 2 is staged: FP64 until that stage stops
- * (stalled, S_max <= max(s_floor, fp64_floor), or the iteration cap), then
+ * (stalled, S_max <= max(s_floor, fp64_floor), its first line-search failure --
+ * past that point FP64 rounding noise decides the Armijo test -- or the
+ * iteration cap), then
  * double-double from the FP64 stage's positions with the energy and gradient
  * re-evaluated, the stall window restarted and the kept (s, y) pairs carried
  * over (a steepest-descent restart with the capped step is far too long this
@@ -209,19 +211,19 @@ typedef struct {
   int32_t max_halvings; /* >= 0                                 */
   int32_t max_ls_fail;  /* >= 1                                 */
   int32_t precision;    /* 0 double-double, 1 FP64, 2 staged    */
-  double fp64_floor;    /* >= 0: S_max floor of the FP64 stage  */
+  double fp64_floor;    /* >= 0: S_max floor of the FP64 stage (e.g. 1e-24) */
   int32_t method;       /* 0 L-BFGS, 1 FIRE                     */
 } ss_min_opts;
 
 /* status: 0 converged (S_max <= s_floor), 1 stalled, 2 iteration cap,
  * 3 non-finite energy (of the last stage run).  iters and evals count every
- * stage; iters_fp64 is the part of iters done in FP64. */
+ * stage; iters_fp64 and evals_fp64 are the parts done in FP64. */
 typedef struct {
   int32_t status;
   int64_t iters, evals, grad_evals;
   double phi[2], smax[2];
   double seconds;
-  int64_t iters_fp64;
+  int64_t iters_fp64, evals_fp64;
 } ss_min_result;
 
 /* Quench pos_dev (double[2][d][N] fractional coordinates, updated in place and

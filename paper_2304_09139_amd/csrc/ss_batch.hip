@@ -491,6 +491,7 @@ extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs
     out[i].smax[1] = hs_.smax[1];
     out[i].seconds = t_stop[i] >= 0.0 ? t_stop[i] : end;
     out[i].iters_fp64 = 0;
+    out[i].evals_fp64 = 0;
   }
   return SS_OK;
 }

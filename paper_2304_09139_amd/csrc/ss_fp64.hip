@@ -37,6 +37,27 @@ __device__ __forceinline__ c64 lds64_entry(const double* tp, int R1, int a, int 
   return c64{e[0], m < 0 ? -e[1] : e[1]};
 }
 
+// the staged particles of one tile, every lane walking the wave's longest piece
+// (L wavevectors) fully unrolled (terms past a lane's own piece are not stored)
+template <int D, int L>
+__device__ __forceinline__ void nk64_tile(const double* __restrict__ lds, int np, int epp, int R1, const Span& sg,
+                                          double (&cr)[kSegLen], double (&ci)[kSegLen]) {
+#pragma unroll 1
+  for (int p = 0; p < np; ++p) {
+    const double* tp = lds + p * epp;
+    c64 w = lds64_entry(tp, R1, D - 1, sg.n[D - 1]);
+#pragma unroll
+    for (int a = 0; a < D - 1; ++a) w = cmul64(w, lds64_entry(tp, R1, a, sg.n[a]));
+    const c64 z = lds64_entry(tp, R1, D - 1, 1);
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      cr[t] += w.re;
+      ci[t] += w.im;
+      if (t + 1 < L) w = cmul64(w, z);
+    }
+  }
+}
+
 // n~(k) partials in FP64: part[(row * 2 + c) * M + slot], c = (C, S), slot order
 template <int D, int PT>
 __global__ void __launch_bounds__(kThreads) k_nk64(const Span* __restrict__ segs, int64_t nseg,
@@ -54,6 +75,8 @@ __global__ void __launch_bounds__(kThreads) k_nk64(const Span* __restrict__ segs
   double cr[kSegLen], ci[kSegLen];
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) cr[t] = ci[t] = 0.0;
+  // pieces are sorted longest first: lane 0 holds the wave's longest piece
+  const int wl = __builtin_amdgcn_readfirstlane(len);
   for (int64_t tile = u.j0; tile < u.j1; tile += PT) {
     const int np = (int)((u.j1 - tile) < PT ? (u.j1 - tile) : PT);
     __syncthreads();
@@ -64,22 +87,16 @@ __global__ void __launch_bounds__(kThreads) k_nk64(const Span* __restrict__ segs
       lds[p * epp + ec] = p < np ? tab[row * N + tile + p] : 0.0;
     }
     __syncthreads();
-    if (len > 0) {
-      for (int p = 0; p < np; ++p) {
-        const double* tp = lds + p * epp;
-        c64 w = lds64_entry(tp, R1, D - 1, sg.n[D - 1]);
-#pragma unroll
-        for (int a = 0; a < D - 1; ++a) w = cmul64(w, lds64_entry(tp, R1, a, sg.n[a]));
-        const c64 z = lds64_entry(tp, R1, D - 1, 1);
-#pragma unroll
-        for (int t = 0; t < kSegLen; ++t) {
-          if (t < len) {
-            cr[t] += w.re;
-            ci[t] += w.im;
-            if (t + 1 < len) w = cmul64(w, z);
-          }
-        }
-      }
+    switch (wl) {
+      case 8: nk64_tile<D, 8>(lds, np, epp, R1, sg, cr, ci); break;
+      case 7: nk64_tile<D, 7>(lds, np, epp, R1, sg, cr, ci); break;
+      case 6: nk64_tile<D, 6>(lds, np, epp, R1, sg, cr, ci); break;
+      case 5: nk64_tile<D, 5>(lds, np, epp, R1, sg, cr, ci); break;
+      case 4: nk64_tile<D, 4>(lds, np, epp, R1, sg, cr, ci); break;
+      case 3: nk64_tile<D, 3>(lds, np, epp, R1, sg, cr, ci); break;
+      case 2: nk64_tile<D, 2>(lds, np, epp, R1, sg, cr, ci); break;
+      case 1: nk64_tile<D, 1>(lds, np, epp, R1, sg, cr, ci); break;
+      default: break;
     }
   }
   double* out = part + (int64_t)u.row * 2 * M;
@@ -212,6 +229,7 @@ __global__ void __launch_bounds__(kThreads) k_grad64(const Span* __restrict__ ru
     double q0 = 0.0, qd = 0.0;
     double nd = (double)run.n[D - 1];
     const double* cp = csw + run.k0;
+#pragma unroll 2
     for (int t = 0; t < run.len; ++t) {
       const double qs = __builtin_fma(cp[M + t], w.re, -(cp[t] * w.im));  // v (S c - C s)
       q0 += qs;

@@ -998,11 +998,15 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
     return err;
   }
   auto last_print = std::chrono::steady_clock::now();
+  int has_prog[kDepth] = {};
+  bool prog_pending = false;
   for (int q = 0; q < kDepth && err == SS_OK; ++q) ok(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "event");
 
   // one stage: a fresh start (history cleared) from the current positions
   const bool fire = op->method == 1;
   auto run_stage = [&](const MinParams& P, int keep) {
+    prog_pending = false;
+    for (int& h : has_prog) h = 0;
     if (!eval(pos_dev, S->f, S->smax, V.g, nullptr)) return;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, S, P, keep);
     ok(hipGetLastError(), "k_init");
@@ -1043,27 +1047,32 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
       }
       const int q = (int)(tick % kDepth);
       if (!ok(hipMemcpyAsync(flags + q, running, sizeof(int32_t), hipMemcpyDeviceToHost, st), "flag copy")) break;
-      if (prog_host) {
+      // a progress record only on a tick enqueued once the interval has passed
+      has_prog[q] = 0;
+      if (prog_host && !prog_pending &&
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - last_print).count() >= progress) {
         hipLaunchKernelGGL(k_progress, dim3(1), dim3(64), 0, st, S, prog_dev);
         if (!ok(hipMemcpyAsync(prog_host + q, prog_dev, sizeof(Progress), hipMemcpyDeviceToHost, st),
                 "progress copy"))
           break;
+        has_prog[q] = 1;
+        prog_pending = true;
       }
       if (!ok(hipEventRecord(ev[q], st), "event record")) break;
       ++tick;
       if (tick >= kDepth) {
         const int w = (int)(tick % kDepth);  // the oldest tick in flight
         if (!ok(hipEventSynchronize(ev[w]), "event sync")) break;
-        if (prog_host) {
+        if (has_prog[w]) {
           const auto now = std::chrono::steady_clock::now();
-          if (std::chrono::duration<double>(now - last_print).count() >= progress) {
-            const Progress& pr = prog_host[w];
-            fprintf(stderr, "[ss_minimize] %s iter %lld evals %lld Phi %.6e S_max %.6e t %.1fs\n",
-                    fp64 ? "fp64" : "dd", (long long)pr.iter, (long long)pr.evals, pr.f, pr.smax,
-                    std::chrono::duration<double>(now - t0).count());
-            fflush(stderr);
-            last_print = now;
-          }
+          const Progress& pr = prog_host[w];
+          fprintf(stderr, "[ss_minimize] %s iter %lld evals %lld Phi %.6e S_max %.6e t %.1fs\n",
+                  fp64 ? "fp64" : "dd", (long long)pr.iter, (long long)pr.evals, pr.f, pr.smax,
+                  std::chrono::duration<double>(now - t0).count());
+          fflush(stderr);
+          last_print = now;
+          has_prog[w] = 0;
+          prog_pending = false;
         }
         if (flags[w] == 0) break;
       }
@@ -1076,19 +1085,28 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
   // kept (s, y) pairs: a restart from steepest descent with the capped step
   // would need far more halvings than allowed this close to a minimum
   MinState hs;
-  int64_t iters_fp64 = 0, evals = 0, iters = 0;
+  int64_t iters_fp64 = 0, evals_fp64 = 0, evals = 0, iters = 0;
   const int prec = op->precision;
   for (int stage = (prec == 0 ? 1 : 0); stage < (prec == 1 ? 1 : 2) && err == SS_OK; ++stage) {
     fp64 = stage == 0;
     MinParams P = min_params(op, prob);
-    if (fp64 && prec == 2) P.s_floor = std::max(op->s_floor, op->fp64_floor);
+    if (fp64 && prec == 2) {
+      // the FP64 stage ends at its own floor or at its first line-search
+      // failure: from there on the FP64 energy's rounding noise decides the
+      // Armijo test and further FP64 steps are wasted
+      P.s_floor = std::max(op->s_floor, op->fp64_floor);
+      P.max_ls_fail = 1;
+    }
     P.max_iter = std::max<int64_t>(0, op->max_iter - iters);
     run_stage(P, (prec == 2 && stage == 1) ? 1 : 0);
     if (err == SS_OK) ok(hipMemcpy(&hs, S, sizeof(MinState), hipMemcpyDeviceToHost), "state copy");
     if (err != SS_OK) break;
     iters += hs.iter;
     evals += hs.evals;
-    if (fp64) iters_fp64 = hs.iter;
+    if (fp64) {
+      iters_fp64 = hs.iter;
+      evals_fp64 = hs.evals;
+    }
     if (hs.status == 3) break;  // non-finite: no second stage
   }
   for (int q = 0; q < kDepth; ++q)
@@ -1101,6 +1119,7 @@ extern "C" int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n
   out->evals = evals;
   out->grad_evals = evals;
   out->iters_fp64 = iters_fp64;
+  out->evals_fp64 = evals_fp64;
   out->phi[0] = hs.f[0];
   out->phi[1] = hs.f[1];
   out->smax[0] = hs.smax[0];

@@ -400,6 +400,7 @@ class Worker {
         r->res.smax[0] = ms.smax[0];
         r->res.smax[1] = ms.smax[1];
         r->res.iters_fp64 = 0;
+        r->res.evals_fp64 = 0;
         r->res.seconds = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
         r->state = 3;
         S->cv.notify_all();

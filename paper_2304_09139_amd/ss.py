@@ -43,7 +43,7 @@ class MinOpts(ctypes.Structure):
 class MinResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int64), ("evals", ctypes.c_int64),
                 ("grad_evals", ctypes.c_int64), ("phi", ctypes.c_double * 2), ("smax", ctypes.c_double * 2),
-                ("seconds", ctypes.c_double), ("iters_fp64", ctypes.c_int64)]
+                ("seconds", ctypes.c_double), ("iters_fp64", ctypes.c_int64), ("evals_fp64", ctypes.c_int64)]
 
 
 class Tile(ctypes.Structure):
@@ -95,7 +95,7 @@ SIGNATURES = {
 }
 
 DEFAULT_MIN_OPTS = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=50, stall_ratio=0.99, c1=1e-4,
-                        step_cap=1e-2, max_halvings=40, max_ls_fail=3, precision=0, fp64_floor=1e-26, method=0)
+                        step_cap=1e-2, max_halvings=40, max_ls_fail=3, precision=0, fp64_floor=1e-24, method=0)
 PRECISION = {"dd": 0, "fp64": 1, "staged": 2}
 METHOD = {"lbfgs": 0, "fire": 1}
 
@@ -154,7 +154,7 @@ STATUS = {0: "converged", 1: "stalled", 2: "max_iter", 3: "numeric"}
 def _result(r) -> dict:
     return dict(status=STATUS.get(r.status, str(r.status)), iters=r.iters, evals=r.evals, grad_evals=r.grad_evals,
                 phi=(r.phi[0], r.phi[1]), smax=(r.smax[0], r.smax[1]), seconds=r.seconds,
-                iters_fp64=r.iters_fp64)
+                iters_fp64=r.iters_fp64, evals_fp64=r.evals_fp64)
 
 
 @dataclass
