@@ -47,6 +47,9 @@ WORKLOADS = {
     # 200 requests served with continuous batching: d in {2, 3}, N log-uniform in
     # [500, 5000], chi uniform in [0.1, 0.49], Poisson arrivals at 0.7 x capacity
     "serve200_d2-3_N500-5000": dict(serve=200, stream_seed=5, cfg_id=6),
+    # the same stream shape at N log-uniform in [1e3, 1e5] (24 requests: the large
+    # ones take seconds each)
+    "serve24_d2-3_N1e3-1e5": dict(serve=24, stream_seed=8, cfg_id=7, n_min=1000, n_max=100000, arena_gb=96),
 }
 
 
@@ -76,6 +79,43 @@ def read_traffic(kernel: str, workload: str) -> float | None:
         return float(rec["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def mp_error_report(ctx, w, n, v, pos, count=6, seed=7):
+    """n~(k) at sampled wavevectors (the smallest |k|, the outermost shell and
+    random ones) from the double-double and the FP64 passes, against a 256-bit
+    mpmath evaluation of the same sums (phases n.u taken exactly from the dd
+    positions): the error of every reported S(k) at those k."""
+    import mpmath
+    import numpy as np
+
+    mp = mpmath.mp.clone() if hasattr(mpmath.mp, "clone") else mpmath.mp
+    mp.prec = 256
+    nd = ctx.energy_grad(w, n, v, pos, grad=False, nk=True)["nk"].cpu().numpy()
+    nf = ctx.energy_grad(w, n, v, pos, grad=False, nk=True, fp64=True)["nk"].cpu().numpy()
+    nh = n.cpu().numpy()
+    ph = pos.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    ks = sorted(set([0, w.M - 1] + [int(k) for k in rng.choice(w.M, count - 2, replace=False)]))
+    u = [[mp.mpf(float(ph[0, a, j])) + mp.mpf(float(ph[1, a, j])) for j in range(w.N)] for a in range(w.d)]
+    rows = []
+    for k in ks:
+        C = mp.mpf(0)
+        S = mp.mpf(0)
+        for j in range(w.N):
+            t = sum(int(nh[k, a]) * u[a][j] for a in range(w.d))
+            t = t - mp.floor(t)
+            C += mp.cospi(2 * t)
+            S += mp.sinpi(2 * t)
+        Sk = (C * C + S * S) / w.N
+        e_dd = max(abs(float(mp.mpf(float(nd[0, k])) + mp.mpf(float(nd[1, k])) - C)),
+                   abs(float(mp.mpf(float(nd[2, k])) + mp.mpf(float(nd[3, k])) - S)))
+        e_64 = max(abs(float(mp.mpf(float(nf[0, k])) - C)), abs(float(mp.mpf(float(nf[2, k])) - S)))
+        sd = (mp.mpf(float(nd[0, k])) + mp.mpf(float(nd[1, k]))) ** 2 + (mp.mpf(float(nd[2, k])) + mp.mpf(float(nd[3, k]))) ** 2
+        rows.append({"k": int(k), "n": [int(x) for x in nh[k]], "S_mp256": float(Sk),
+                     "abs_err_S_dd": float(abs(sd / w.N - Sk)), "abs_err_nk_dd": e_dd, "abs_err_nk_fp64": e_64})
+    return {"sampled_k": rows, "max_abs_err_nk_dd_over_N": max(r["abs_err_nk_dd"] for r in rows) / w.N,
+            "max_abs_err_nk_fp64_over_N": max(r["abs_err_nk_fp64"] for r in rows) / w.N}
 
 
 def cpu_baseline(d, N, chi, cfg_id):
@@ -116,6 +156,8 @@ def main():
                     help="seconds between the library's progress lines on stderr (0: none)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched workloads: skip timing the same configurations one at a time")
+    ap.add_argument("--mp-report", action="store_true",
+                    help="report the 256-bit error of n~ at sampled k of the final configuration")
     ap.add_argument("--method", default="lbfgs", choices=("lbfgs", "fire"),
                     help="minimiser of the single-configuration quench")
     ap.add_argument("--precision", default="dd", choices=("dd", "staged", "fp64"),
@@ -267,6 +309,9 @@ def main():
             "launches": launches,
         },
     }
+    if args.precision == "staged" or args.mp_report:
+        # 256-bit error of the reported n~ / S(k) at the final positions of the last quench
+        out["error_vs_mp256_final"] = mp_error_report(ctx, w, n, v, starts[args.warmup + args.steps - 1])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, N, chi, wl["cfg_id"])
     print(json.dumps(out), flush=True)
@@ -378,11 +423,12 @@ def bench_serve(args, wl):
     from paper_2304_09139_amd.tune import load_tiles
 
     count = wl["serve"]
-    stream = inputs.serve_stream(count, seed=wl["stream_seed"])
+    n_min, n_max = wl.get("n_min", 500), wl.get("n_max", 5000)
+    stream = inputs.serve_stream(count, seed=wl["stream_seed"], n_min=n_min, n_max=n_max)
     works = [ss.Workload.from_chi(d, N, chi) for d, N, chi, _ in stream]
     starts = [inputs.config_positions(wl["cfg_id"], w.d, w.N, i) for i, w in enumerate(works)]
     ctx = ss.Context(0, tiles="tuned")
-    arena = 8 << 30
+    arena = wl.get("arena_gb", 8) << 30
     ctx.server_start(arena, max_slots=512)
 
     def run(times):
@@ -401,6 +447,9 @@ def bench_serve(args, wl):
                     r = ctx.poll(t)
                     if r is not None:
                         done[k] = r[0]
+                        if count <= 50:  # long requests: a line per completion
+                            print(f"[serve] {len(done)}/{count} done, t {time.perf_counter() - t0:.1f}s",
+                                  file=sys.stderr, flush=True)
             time.sleep(0.0005)
         return time.perf_counter() - t0, [done[k] for k in range(count)]
 
@@ -431,8 +480,8 @@ def bench_serve(args, wl):
         "dtype": "dd",
         "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
         "config": {"workload": f"{count} served L-BFGS quenches to S_max <= {FLOOR:g}, d in {{2,3}}, "
-                               f"N log-uniform in [500, 5000], chi uniform in [0.1, 0.49], Poisson arrivals "
-                               f"at 0.7 x capacity", "requests": count, "s_floor": FLOOR,
+                               f"N log-uniform in [{n_min}, {n_max}], chi uniform in [0.1, 0.49], Poisson "
+                               f"arrivals at 0.7 x capacity", "requests": count, "s_floor": FLOOR,
                    "parallelism": "single GPU"},
         "configs_per_s": conv / open_s,
         "converged": f"{conv}/{count}",

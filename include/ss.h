@@ -251,7 +251,7 @@ int ss_minimize(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const
 
 /* One entry of the tile table: used for problems with d == this d (0 = any d),
  * N <= max_N and M <= max_M; the first matching entry wins, and problems that
- * match none use nk_chunk = 64, grad_k = 1024. */
+ * match none use nk_chunk = max(64, ceil(N / 256)), grad_k = 1024. */
 typedef struct {
   int32_t d;
   int64_t max_N, max_M;

@@ -394,7 +394,9 @@ namespace ss {
 TileSpec tile_for(ss_ctx* ctx, int d, int64_t N, int64_t M) {
   for (const ss_tile_entry& e : ctx->tiles)
     if ((e.d == 0 || e.d == d) && N <= e.max_N && M <= e.max_M) return e.t;
-  return TileSpec{kDefaultNkChunk, kDefaultGradK};
+  // built-in shape: at most kMaxNkRows partial rows, so the partial sums stay
+  // within 32 kMaxNkRows M bytes however large N is
+  return TileSpec{std::max<int64_t>(kDefaultNkChunk, (N + kMaxNkRows - 1) / kMaxNkRows), kDefaultGradK};
 }
 
 // the batched shape of a problem: plan, layout, n(k) schedule and gradient chunks

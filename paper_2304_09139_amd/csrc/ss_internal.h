@@ -97,6 +97,7 @@ constexpr int kCombK = 32;        // wavevectors per block of the partial combin
 constexpr int kXcds = 8;          // accelerator complex dies (one L2 each); workgroups are dealt round-robin
 constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)
 constexpr int64_t kDefaultGradK = 1024;
+constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks per n(k) piece block
 
 }  // namespace ss
 

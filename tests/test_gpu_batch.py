@@ -125,6 +125,9 @@ def test_tiles_and_errors(ctx):
     assert ctx.get_tile(w) == dict(nk_chunk=32, grad_k=256)
     w3 = ss.Workload.from_chi(3, 300, 0.3)
     assert ctx.get_tile(w3) == dict(nk_chunk=64, grad_k=1024)
+    # built-in shape for large N: at most 256 partial rows
+    big = ss.Workload(2, 100000, 100, ss.count(2, 100), 1.0, 0)
+    assert ctx.get_tile(big) == dict(nk_chunk=391, grad_k=1024)
     # a different tile still satisfies the parity gate against the oracle
     x = dev(pos)
     r = ctx.minimize_batch([w], [x], opts=dict(max_iter=3, s_floor=0.0))[0]
