@@ -192,29 +192,33 @@ def test_invalid_arguments(ctx):
     assert rc == ss.SS_EINVAL
 
 
-@pytest.mark.parametrize("d,N,chi,nk_samples,grad_samples", [(3, 8000, 0.45, 32, 12)])
-def test_full_size_sampled(ctx, d, N, chi, nk_samples, grad_samples):
-    """The d=3, N=8000, chi=0.45 evaluation at full size: n~ at sampled k and the
-    gradient at sampled particles against the oracle (which needs all n~ for the
-    gradient, computed on the host cores)."""
+@pytest.mark.parametrize("d,N,chi,vkind,cfg,nk_samples,grad_samples",
+                         [(3, 8000, 0.45, 0, 2, 32, 12), (3, 30000, 0.45, 1, 4, 32, 8)])
+def test_full_size_sampled(ctx, d, N, chi, vkind, cfg, nk_samples, grad_samples):
+    """The d=3, N=8000, chi=0.45 and the weighted d=3, N=30000, chi=0.45
+    evaluations at full size, in the launch shape the benchmark times: n~ at
+    sampled k and the gradient at sampled particles against the oracle (which
+    needs all n~ for the gradient, computed on the host cores)."""
     R2, M = ss.cutoff(d, N, chi)
-    w = ss.Workload(d, N, R2, M)
-    pos = inputs.config_positions(2, d, N, 0)
+    w = ss.Workload(d, N, R2, M, 1.0, vkind)
+    pos = inputs.config_positions(cfg, d, N, 0)
     n_t = ctx.wavevectors(d, R2)
-    out = ctx.energy_grad(w, n_t, None, dev(pos), grad=True, nk=True)
+    v_t = ctx.weights(w, n_t) if vkind else None
+    out = ctx.energy_grad(w, n_t, v_t, dev(pos), grad=True, nk=True)
     got = {k: host(t) for k, t in out.items()}
     n = host(n_t)
+    v = O.weights(n, R2, vkind) if vkind else None
     rng = np.random.default_rng(0)
     ks = np.unique(np.concatenate([[0, M - 1], rng.choice(M, nk_samples, replace=False)]))
     ref_nk = O.nk(n, pos)                     # all k: needed by the gradient
     dC = np.abs(dd_diff(got["nk"][0, ks], got["nk"][1, ks], ref_nk[0, ks], ref_nk[1, ks]))
     dS = np.abs(dd_diff(got["nk"][2, ks], got["nk"][3, ks], ref_nk[2, ks], ref_nk[3, ks]))
     assert dC.max() <= TOL * N and dS.max() <= TOL * N
-    e = O.energy_from_nk(N, None, ref_nk)
+    e = O.energy_from_nk(N, v, ref_nk)
     assert abs(dd_diff(got["phi"][0], got["phi"][1], e.phi[0], e.phi[1])) <= TOL * e.phi[0]
     js = np.unique(np.concatenate([[0, N - 1], rng.choice(N, grad_samples, replace=False)]))
-    g = O.grad(n, None, pos, ref_nk, js=js)      # [nj, d, 2]
-    G = grad_scale(n, None, ref_nk)
+    g = O.grad(n, v, pos, ref_nk, js=js)      # [nj, d, 2]
+    G = grad_scale(n, v, ref_nk)
     for q, j in enumerate(js):
         for a in range(d):
             diff = abs(dd_diff(got["grad"][0, a, j], got["grad"][1, a, j], g[q, a, 0], g[q, a, 1]))
