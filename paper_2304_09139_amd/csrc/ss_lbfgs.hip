@@ -67,7 +67,7 @@ __device__ __forceinline__ const double* vec_of(const VecSet& V, int code) {
 __device__ __forceinline__ dd vload(const double* p, int64_t nv, int64_t i) { return dd{p[i], p[nv + i]}; }
 
 // ---------------------------------------------------------------------------
-// the direction (run by the last block of the direction products; rows live on
+// the direction (run by the one block that finishes the direction products; rows live on
 // lanes i < k of wave 0).  Compact form with H0 = gamma I:
 //   H g = gamma g + S top - gamma Y z,  R z = u,  R^T top = D z + gamma (Y^T Y z - w)
 // with u = S^T g, w = Y^T g, R the upper triangle of S^T Y and D its diagonal.
@@ -301,7 +301,7 @@ __device__ __forceinline__ void init_body(MinState* S_, const MinParams& P, int 
 
 __global__ void __launch_bounds__(64) k_init(MinState* S_, MinParams P, int keep) { init_body(S_, P, keep); }
 
-// the Armijo test and its consequences (run by the last block of the trial
+// the Armijo test and its consequences (run by the one block that finishes the trial
 // products; all threads call it for the barriers, wave 0 does the work).  Lane 0
 // takes the decisions and hands them to the other lanes through LDS.
 __device__ void decide_logic(MinState& S, const MinParams& P, int i) {
