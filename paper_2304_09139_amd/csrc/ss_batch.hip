@@ -52,8 +52,8 @@ int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot
     ctx->last_error = "invalid minimiser options";
     return SS_EINVAL;
   }
-  if (op->precision != 0 || op->method != 0) {
-    ctx->last_error = "batched quenches run L-BFGS in double-double only (precision 0, method 0)";
+  if (op->method != 0) {
+    ctx->last_error = "batched quenches run L-BFGS (method 0)";
     return SS_EINVAL;
   }
   h->prob = *p;
@@ -71,7 +71,20 @@ int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot
   h->n_dots = (int64_t)h->G * (2 * h->m + 2);
   h->n_vec = (h->nv + kThreads - 1) / kThreads;
   h->work = (double)p->M * (double)p->N;
+  h->phase = op->precision == 0 ? 1 : 0;
   return SS_OK;
+}
+
+MinParams stage_params(const HostSlot& h, int64_t iters_done) {
+  MinParams P = min_params(&h.opts, &h.prob);
+  if (h.phase == 0 && h.opts.precision == 2) {
+    // the FP64 stage of a staged quench ends at its own floor or its first
+    // line-search failure (as in ss_minimize)
+    P.s_floor = std::max(h.opts.s_floor, h.opts.fp64_floor);
+    P.max_ls_fail = 1;
+  }
+  P.max_iter = std::max<int64_t>(0, h.opts.max_iter - iters_done);
+  return P;
 }
 
 // work lists of the configurations in `active` (largest first within every launch)
@@ -91,35 +104,47 @@ void build_lists(const std::vector<HostSlot>& hs, std::vector<int> active, std::
     L.table_work += (double)hs[s].prob.d * hs[s].c.R1 * hs[s].prob.N;
   }
   L.table_n = (int64_t)U.size() - L.table_off;
-  // n(k) pass grouped by (d, LDS tile)
-  for (int d = 1; d <= 4; ++d)
-    for (int pt : {16, 4, 1}) {
-      Lists::Group g{d, pt, 0, (int64_t)U.size(), 0, 0.0};
+  // the pair passes, separately for the configurations in double-double (phase 1)
+  // and in FP64 (phase 0)
+  for (int ph = 1; ph >= 0; --ph) {
+    auto& nkg = ph ? L.nk : L.nk64;
+    auto& grg = ph ? L.grad : L.grad64;
+    // n(k) pass grouped by (d, LDS tile)
+    for (int d = 1; d <= 4; ++d)
+      for (int pt : {16, 4, 1}) {
+        Lists::Group g{d, pt, 0, (int64_t)U.size(), 0, 0.0};
+        for (int s : active)
+          if (hs[s].phase == ph && hs[s].prob.d == d && hs[s].c.pt == pt) {
+            add(hs[s].n_nk, s);
+            g.R1max = std::max(g.R1max, hs[s].c.R1);
+            g.pairs += hs[s].work;
+          }
+        g.n = (int64_t)U.size() - g.off;
+        if (g.n > 0) nkg.push_back(g);
+      }
+    int64_t& co = ph ? L.comb_off : L.comb64_off;
+    int64_t& cn = ph ? L.comb_n : L.comb64_n;
+    co = (int64_t)U.size();
+    for (int s : active)
+      if (hs[s].phase == ph) add(hs[s].n_comb, s);
+    cn = (int64_t)U.size() - co;
+    for (int d = 1; d <= 4; ++d) {
+      Lists::Group g{d, 0, 0, (int64_t)U.size(), 0, 0.0};
       for (int s : active)
-        if (hs[s].prob.d == d && hs[s].c.pt == pt) {
-          add(hs[s].n_nk, s);
-          g.R1max = std::max(g.R1max, hs[s].c.R1);
+        if (hs[s].phase == ph && hs[s].prob.d == d) {
+          add(hs[s].n_grad, s);
           g.pairs += hs[s].work;
         }
       g.n = (int64_t)U.size() - g.off;
-      if (g.n > 0) L.nk.push_back(g);
+      if (g.n > 0) grg.push_back(g);
     }
-  L.comb_off = (int64_t)U.size();
-  for (int s : active) add(hs[s].n_comb, s);
-  L.comb_n = (int64_t)U.size() - L.comb_off;
-  for (int d = 1; d <= 4; ++d) {
-    Lists::Group g{d, 0, 0, (int64_t)U.size(), 0, 0.0};
+    int64_t& go = ph ? L.gcomb_off : L.gcomb64_off;
+    int64_t& gn = ph ? L.gcomb_n : L.gcomb64_n;
+    go = (int64_t)U.size();
     for (int s : active)
-      if (hs[s].prob.d == d) {
-        add(hs[s].n_grad, s);
-        g.pairs += hs[s].work;
-      }
-    g.n = (int64_t)U.size() - g.off;
-    if (g.n > 0) L.grad.push_back(g);
+      if (hs[s].phase == ph) add(hs[s].n_gcomb, s);
+    gn = (int64_t)U.size() - go;
   }
-  L.gcomb_off = (int64_t)U.size();
-  for (int s : active) add(hs[s].n_gcomb, s);
-  L.gcomb_n = (int64_t)U.size() - L.gcomb_off;
   L.dots_off = (int64_t)U.size();
   for (int s : active) add(hs[s].n_dots, s);
   L.dots_n = (int64_t)U.size() - L.dots_off;
@@ -135,7 +160,7 @@ struct Header {
   MinSlot* ms;
   BUnit* units;
   int32_t* list;
-  int32_t* flags;
+  SlotFlags* flags;
   size_t bytes;
 };
 
@@ -146,7 +171,7 @@ void header_offsets(int count, int64_t ucap, size_t off[6]) {
   off[2] = off[1] + al256(sizeof(MinSlot) * count);
   off[3] = off[2] + al256(sizeof(BUnit) * (size_t)std::max<int64_t>(ucap, 1));
   off[4] = off[3] + al256(sizeof(int32_t) * count);
-  off[5] = off[4] + al256(sizeof(int32_t) * count);
+  off[5] = off[4] + al256(sizeof(SlotFlags) * count);
 }
 
 Header carve_header(char* base, int count, int64_t ucap) {
@@ -157,7 +182,7 @@ Header carve_header(char* base, int count, int64_t ucap) {
   h.ms = (MinSlot*)(base + off[1]);
   h.units = (BUnit*)(base + off[2]);
   h.list = (int32_t*)(base + off[3]);
-  h.flags = (int32_t*)(base + off[4]);
+  h.flags = (SlotFlags*)(base + off[4]);
   h.bytes = off[5];
   return h;
 }
@@ -208,7 +233,8 @@ void fill_slot(const HostSlot& h, char* mem, double* x, const double* v, EvalSlo
   for (int i = 0; i <= h.m; ++i) V.Y[i] = (double*)take(vec);
   C->S = (MinState*)take(al256(sizeof(MinState)));
   C->partial = (double*)take(al256(sizeof(double) * 2 * (2 * h.m + 2) * h.G));
-  C->P = min_params(&h.opts, &h.prob);
+  C->P = stage_params(h, 0);
+  C->keep = 0;
   C->eblk = E->blk;
   C->neblk = c.combine_blocks;
   C->nv = h.nv;
@@ -237,7 +263,20 @@ hipError_t launch_eval(ss_ctx* ctx, const DevArrays& D, const Lists& L, int whic
     e = timed(ctx, 1, st, g.pairs, [&] { return launch_batch_grad(g.d, D.es, D.units + g.off, g.n, gate, st); });
     if (e != hipSuccess) return e;
   }
-  return launch_batch_gcomb(D.es, D.units + L.gcomb_off, L.gcomb_n, which, gate, st);
+  e = launch_batch_gcomb(D.es, D.units + L.gcomb_off, L.gcomb_n, which, gate, st);
+  if (e != hipSuccess) return e;
+  // configurations in their FP64 stage
+  for (const auto& g : L.nk64) {
+    e = launch_batch_nk64(g.d, g.pt, g.R1max, D.es, D.units + g.off, g.n, gate, st);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_batch_combine64(D.es, D.units + L.comb64_off, L.comb64_n, gate, st);
+  if (e != hipSuccess) return e;
+  for (const auto& g : L.grad64) {
+    e = launch_batch_grad64(g.d, D.es, D.units + g.off, g.n, gate, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_batch_gcomb64(D.es, D.units + L.gcomb64_off, L.gcomb64_n, which, gate, st);
 }
 
 hipError_t launch_start(ss_ctx* ctx, const DevArrays& D, const Lists& L, hipStream_t st) {
@@ -394,10 +433,12 @@ extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs
   // pinned staging: descriptors, unit lists, flag ring, final states
   const size_t desc_bytes = sizeof(EvalSlot) * count + sizeof(MinSlot) * count;
   const size_t list_bytes = sizeof(BUnit) * (size_t)std::max<int64_t>(ucap, 1) + sizeof(int32_t) * count;
-  Pinned pin_desc, pin_list, pin_flags, pin_state;
+  constexpr int kStages = 4;  // list uploads in flight
+  Pinned pin_desc, pin_list[kStages], pin_flags, pin_state;
   if (!ok(hipHostMalloc(&pin_desc.p, desc_bytes, hipHostMallocDefault), "hipHostMalloc")) return err;
-  if (!ok(hipHostMalloc(&pin_list.p, list_bytes, hipHostMallocDefault), "hipHostMalloc")) return err;
-  if (!ok(hipHostMalloc(&pin_flags.p, sizeof(int32_t) * count * kDepth, hipHostMallocDefault), "hipHostMalloc"))
+  for (auto& pl : pin_list)
+    if (!ok(hipHostMalloc(&pl.p, list_bytes, hipHostMallocDefault), "hipHostMalloc")) return err;
+  if (!ok(hipHostMalloc(&pin_flags.p, sizeof(SlotFlags) * count * kDepth, hipHostMallocDefault), "hipHostMalloc"))
     return err;
   if (!ok(hipHostMalloc(&pin_state.p, sizeof(MinState) * count, hipHostMallocDefault), "hipHostMalloc")) return err;
   memcpy(pin_desc.p, es.data(), sizeof(EvalSlot) * count);
@@ -407,53 +448,90 @@ extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs
                     hipMemcpyHostToDevice, st),
      "descriptor copy");
 
-  hipEvent_t ev[kDepth] = {}, ev_up = nullptr;
+  hipEvent_t ev[kDepth] = {}, ev_up[kStages] = {};
   for (int q = 0; q < kDepth && err == SS_OK; ++q) ok(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming), "event");
-  ok(hipEventCreateWithFlags(&ev_up, hipEventDisableTiming), "event");
-  bool up_pending = false;
+  for (int q = 0; q < kStages && err == SS_OK; ++q)
+    ok(hipEventCreateWithFlags(&ev_up[q], hipEventDisableTiming), "event");
+  bool up_pending[kStages] = {};
+  int up_next = 0;
 
   std::vector<BUnit> U;
   std::vector<int32_t> list;
   Lists L;
+  const DevArrays D{H.es, H.ms, H.units, H.list, H.flags};
+  // work lists go through a ring of pinned staging buffers, each reused once its
+  // previous copy has completed; stream order keeps the device copy behind the
+  // launches that read the previous lists
   auto upload = [&](const std::vector<int>& active) {
     build_lists(hs, active, U, list, L);
-    if (up_pending && !ok(hipEventSynchronize(ev_up), "event sync")) return false;
-    memcpy(pin_list.p, U.data(), sizeof(BUnit) * U.size());
-    memcpy((char*)pin_list.p + sizeof(BUnit) * ucap, list.data(), sizeof(int32_t) * list.size());
-    if (!U.empty()) ok(hipMemcpyAsync(H.units, pin_list.p, sizeof(BUnit) * U.size(), hipMemcpyHostToDevice, st), "list copy");
-    ok(hipMemcpyAsync(H.list, (char*)pin_list.p + sizeof(BUnit) * ucap, sizeof(int32_t) * list.size(),
-                      hipMemcpyHostToDevice, st),
+    const int k = up_next;
+    up_next = (up_next + 1) % kStages;
+    if (up_pending[k] && !ok(hipEventSynchronize(ev_up[k]), "event sync")) return false;
+    char* pl = (char*)pin_list[k].p;
+    memcpy(pl, U.data(), sizeof(BUnit) * U.size());
+    memcpy(pl + sizeof(BUnit) * ucap, list.data(), sizeof(int32_t) * list.size());
+    if (!U.empty()) ok(hipMemcpyAsync(H.units, pl, sizeof(BUnit) * U.size(), hipMemcpyHostToDevice, st), "list copy");
+    ok(hipMemcpyAsync(H.list, pl + sizeof(BUnit) * ucap, sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, st),
        "list copy");
-    ok(hipEventRecord(ev_up, st), "event record");
-    up_pending = true;
+    ok(hipEventRecord(ev_up[k], st), "event record");
+    up_pending[k] = true;
     return err == SS_OK;
   };
-  const DevArrays D{H.es, H.ms, H.units, H.list, H.flags};
+  // staged quenches whose FP64 stage has stopped continue in double-double from
+  // their positions: new stage parameters (the kept pairs are carried over),
+  // the double-double starting evaluation and tests, then back to the lists
+  std::vector<int64_t> iters64(count, 0), evals64(count, 0);
+  // flags of ticks enqueued before a configuration's switch still show its
+  // stopped FP64 stage: they are read only from this tick on
+  std::vector<int64_t> valid_from(count, 0);
+  int64_t tick = 0;
+  MinSlot* ms_pin = (MinSlot*)((char*)pin_desc.p + sizeof(EvalSlot) * count);
+  auto switch_to_dd = [&](const std::vector<int>& sw, const std::vector<int>& active_now) {
+    for (int s : sw) {
+      hs[s].phase = 1;
+      valid_from[s] = tick;
+      ms_pin[s].P = stage_params(hs[s], iters64[s]);
+      ms_pin[s].keep = 1;
+      // the previous copy from this cell finished before the first step ran
+      if (!ok(hipMemcpyAsync(H.ms + s, ms_pin + s, sizeof(MinSlot), hipMemcpyHostToDevice, st), "descriptor copy"))
+        return false;
+    }
+    if (!upload(sw) || !ok(launch_start(ctx, D, L, st), "batched restart")) return false;
+    return upload(active_now);
+  };
   std::vector<int> active(count);
   std::iota(active.begin(), active.end(), 0);
   std::vector<double> t_stop(count, -1.0);
   // the starting evaluation and the first tests of every configuration
   if (upload(active)) ok(launch_start(ctx, D, L, st), "batched start");
-  int64_t tick = 0;
   double last_print = 0.0;
   while (err == SS_OK) {
     if (!ok(launch_tick(ctx, D, L, st), "batched step")) break;
     const int q = (int)(tick % kDepth);
-    int32_t* hf = (int32_t*)pin_flags.p + (size_t)q * count;
-    if (!ok(hipMemcpyAsync(hf, H.flags, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st), "flag copy")) break;
+    SlotFlags* hf = (SlotFlags*)pin_flags.p + (size_t)q * count;
+    if (!ok(hipMemcpyAsync(hf, H.flags, sizeof(SlotFlags) * count, hipMemcpyDeviceToHost, st), "flag copy")) break;
     if (!ok(hipEventRecord(ev[q], st), "event record")) break;
     ++tick;
     if (tick < kDepth) continue;
     const int w = (int)(tick % kDepth);  // the oldest step in flight
     if (!ok(hipEventSynchronize(ev[w]), "event sync")) break;
-    const int32_t* f = (int32_t*)pin_flags.p + (size_t)w * count;
+    const SlotFlags* f = (SlotFlags*)pin_flags.p + (size_t)w * count;
     // the flags of step tick - kDepth cover the configurations listed then,
     // which include every configuration listed now
-    std::vector<int> still;
+    std::vector<int> still, sw;
     const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const int64_t seen = tick - kDepth;  // the tick these flags come from
     for (int s : active) {
-      if (f[s]) still.push_back(s);
-      else if (t_stop[s] < 0.0) t_stop[s] = now;
+      if (f[s].running || seen < valid_from[s]) {
+        still.push_back(s);
+      } else if (hs[s].phase == 0 && hs[s].opts.precision == 2 && f[s].status != 3) {
+        iters64[s] = f[s].iter;  // the FP64 stage's totals
+        evals64[s] = f[s].evals;
+        sw.push_back(s);
+        still.push_back(s);
+      } else if (t_stop[s] < 0.0) {
+        t_stop[s] = now;
+      }
     }
     if (ctx->progress_interval > 0.0 && now - last_print >= ctx->progress_interval) {
       fprintf(stderr, "[ss_minimize_batch] step %lld: %zu of %d configurations running, t %.1fs\n",
@@ -462,7 +540,10 @@ extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs
       last_print = now;
     }
     if (still.empty()) break;
-    if (still.size() < active.size()) {
+    if (!sw.empty()) {
+      active = still;
+      if (!switch_to_dd(sw, active)) break;
+    } else if (still.size() < active.size()) {
       active = still;
       if (!upload(active)) break;
     }
@@ -476,22 +557,25 @@ extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs
   }
   for (int q = 0; q < kDepth; ++q)
     if (ev[q]) hipEventDestroy(ev[q]);
-  if (ev_up) hipEventDestroy(ev_up);
+  for (int q = 0; q < kStages; ++q)
+    if (ev_up[q]) hipEventDestroy(ev_up[q]);
   if (err != SS_OK) return err;
   const double end = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int i = 0; i < count; ++i) {
     const MinState& hs_ = ((MinState*)pin_state.p)[i];
     out[i].status = hs_.status;
-    out[i].iters = hs_.iter;
-    out[i].evals = hs_.evals;
-    out[i].grad_evals = hs_.evals;
+    out[i].iters = hs_.iter + iters64[i];
+    out[i].evals = hs_.evals + evals64[i];
+    out[i].grad_evals = out[i].evals;
     out[i].phi[0] = hs_.f[0];
     out[i].phi[1] = hs_.f[1];
     out[i].smax[0] = hs_.smax[0];
     out[i].smax[1] = hs_.smax[1];
     out[i].seconds = t_stop[i] >= 0.0 ? t_stop[i] : end;
-    out[i].iters_fp64 = 0;
-    out[i].evals_fp64 = 0;
+    // FP64-only quenches never switch: all their iterations are FP64
+    const bool all64 = hs[i].opts.precision == 1;
+    out[i].iters_fp64 = all64 ? hs_.iter : iters64[i];
+    out[i].evals_fp64 = all64 ? hs_.evals : evals64[i];
   }
   return SS_OK;
 }

@@ -32,7 +32,13 @@ hipError_t launch_batch_dots_final(const MinSlot* ms, const int32_t* list, int64
 hipError_t launch_batch_step(const MinSlot* ms, const BUnit* units, int64_t n, hipStream_t st);
 hipError_t launch_batch_accept(const MinSlot* ms, const BUnit* units, int64_t n, hipStream_t st);
 hipError_t launch_batch_init(const MinSlot* ms, const int32_t* list, int64_t n, hipStream_t st);
-hipError_t launch_batch_flags(const MinSlot* ms, const int32_t* list, int64_t n, int32_t* out, hipStream_t st);
+hipError_t launch_batch_flags(const MinSlot* ms, const int32_t* list, int64_t n, SlotFlags* out, hipStream_t st);
+hipError_t launch_batch_nk64(int d, int pt, int R1max, const EvalSlot* es, const BUnit* units, int64_t n, int gate,
+                             hipStream_t st);
+hipError_t launch_batch_combine64(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
+hipError_t launch_batch_grad64(int d, const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
+hipError_t launch_batch_gcomb64(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
+                                hipStream_t st);
 
 
 namespace eng {
@@ -50,6 +56,7 @@ struct HostSlot {
   // unit counts of this configuration's grids
   int64_t n_table = 0, n_nk = 0, n_comb = 0, n_grad = 0, n_gcomb = 0, n_dots = 0, n_vec = 0;
   double work = 0.0;  // M N, for ordering
+  int phase = 1;      // evaluation precision now: 0 FP64 (first stage or FP64 only), 1 double-double
 };
 
 // offsets and counts of each batched launch inside the unit array
@@ -61,6 +68,9 @@ struct Lists {
   };
   double table_work = 0.0;
   int64_t table_off = 0, table_n = 0, comb_off = 0, comb_n = 0, gcomb_off = 0, gcomb_n = 0;
+  // configurations evaluating in FP64 (staged quenches before their switch)
+  int64_t comb64_off = 0, comb64_n = 0, gcomb64_off = 0, gcomb64_n = 0;
+  std::vector<Group> nk64, grad64;
   int64_t dots_off = 0, dots_n = 0, vec_off = 0, vec_n = 0;
   std::vector<Group> nk, grad;
   int64_t nlist = 0;
@@ -72,7 +82,7 @@ struct DevArrays {
   MinSlot* ms;
   BUnit* units;
   int32_t* list;
-  int32_t* flags;
+  SlotFlags* flags;
 };
 
 size_t al256(size_t x);
@@ -82,6 +92,8 @@ int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot
 void build_lists(const std::vector<HostSlot>& hs, std::vector<int> active, std::vector<BUnit>& U,
                  std::vector<int32_t>& list, Lists& L);
 void fill_slot(const HostSlot& h, char* mem, double* x, const double* v, EvalSlot* E, MinSlot* C);
+// the minimiser parameters of a configuration's current stage
+MinParams stage_params(const HostSlot& h, int64_t iters_done);
 // the starting evaluation and tests of every listed configuration
 hipError_t launch_start(ss_ctx* ctx, const DevArrays& D, const Lists& L, hipStream_t st);
 // one minimiser step of every listed configuration, ending with the gather of

@@ -19,6 +19,7 @@
 
 #include "ss_dd.h"
 #include "ss_internal.h"
+#include "ss_min.h"
 
 namespace ss {
 
@@ -60,14 +61,11 @@ __device__ __forceinline__ void nk64_tile(const double* __restrict__ lds, int np
 
 // n~(k) partials in FP64: part[(row * 2 + c) * M + slot], c = (C, S), slot order
 template <int D, int PT>
-__global__ void __launch_bounds__(kThreads) k_nk64(const Span* __restrict__ segs, int64_t nseg,
-                                                   const NkUnit* __restrict__ units, const double* __restrict__ tab,
-                                                   int64_t N, int R1, double* __restrict__ part, int64_t M,
-                                                   const SlotOffsets so, const int* __restrict__ active) {
-  if (active && *active == 0) return;
-  extern __shared__ double lds[];  // [PT][D][R1][2]
+__device__ __forceinline__ void nk64_body(const Span* __restrict__ segs, int64_t nseg, const NkUnit u,
+                                          const double* __restrict__ tab, int64_t N, int R1,
+                                          double* __restrict__ part, int64_t M, const SlotOffsets& so,
+                                          double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  const NkUnit u = units[blockIdx.x];
   const int64_t s = (int64_t)u.block * kNkPieces + tid;
   const Span sg = segs[s < nseg ? s : nseg - 1];
   const int len = s < nseg ? sg.len : 0;
@@ -110,23 +108,30 @@ __global__ void __launch_bounds__(kThreads) k_nk64(const Span* __restrict__ segs
   }
 }
 
+template <int D, int PT>
+__global__ void __launch_bounds__(kThreads) k_nk64(const Span* __restrict__ segs, int64_t nseg,
+                                                   const NkUnit* __restrict__ units, const double* __restrict__ tab,
+                                                   int64_t N, int R1, double* __restrict__ part, int64_t M,
+                                                   const SlotOffsets so, const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  extern __shared__ double lds[];  // [PT][D][R1][2]
+  nk64_body<D, PT>(segs, nseg, units[blockIdx.x], tab, N, R1, part, M, so, lds);
+}
+
 // combine the FP64 partials (fixed order); n~ (dd layout, zero low words) in
 // canonical order, (v C, v S) in walk order as csw[2][M], and per-block Phi and
 // S_max partials in the double-double block layout
-__global__ void __launch_bounds__(kThreads) k_nk_combine64(const double* __restrict__ part,
-                                                           const int32_t* __restrict__ rows_of,
-                                                           const int32_t* __restrict__ k_of_slot, int64_t M,
-                                                           int64_t N, const int32_t* __restrict__ canon_of_lex,
-                                                           const double* __restrict__ v, double* __restrict__ nk_out,
-                                                           double* __restrict__ csw, double* __restrict__ blk,
-                                                           const int* __restrict__ active) {
-  if (active && *active == 0) return;
+__device__ __forceinline__ void combine64_body(const double* __restrict__ part, const int32_t* __restrict__ rows_of,
+                                               const int32_t* __restrict__ k_of_slot, int64_t M, int64_t N,
+                                               const int32_t* __restrict__ canon_of_lex,
+                                               const double* __restrict__ v, double* __restrict__ nk_out,
+                                               double* __restrict__ csw, double* __restrict__ blk, int64_t bidx) {
   constexpr int kCombG = kThreads / kCombK;
   __shared__ double s_c[kCombG][2][kCombK];
   __shared__ double s_ph[kCombK], s_mh[kCombK];
   __shared__ int64_t s_mk[kCombK];
   const int tid = threadIdx.x, q = tid % kCombK, g = tid / kCombK;
-  const int64_t i = (int64_t)blockIdx.x * kCombK + q;
+  const int64_t i = bidx * kCombK + q;
   double C = 0.0, S = 0.0;
   if (i < M) {
     const int64_t P = rows_of[i];
@@ -183,13 +188,24 @@ __global__ void __launch_bounds__(kThreads) k_nk_combine64(const double* __restr
     __syncthreads();
   }
   if (tid == 0) {
-    double* b = blk + (int64_t)blockIdx.x * 5;
+    double* b = blk + bidx * 5;
     b[0] = s_ph[0];
     b[1] = 0.0;
     b[2] = s_mh[0];
     b[3] = 0.0;
     b[4] = (double)s_mk[0];
   }
+}
+
+__global__ void __launch_bounds__(kThreads) k_nk_combine64(const double* __restrict__ part,
+                                                           const int32_t* __restrict__ rows_of,
+                                                           const int32_t* __restrict__ k_of_slot, int64_t M,
+                                                           int64_t N, const int32_t* __restrict__ canon_of_lex,
+                                                           const double* __restrict__ v, double* __restrict__ nk_out,
+                                                           double* __restrict__ csw, double* __restrict__ blk,
+                                                           const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  combine64_body(part, rows_of, k_of_slot, M, N, canon_of_lex, v, nk_out, csw, blk, blockIdx.x);
 }
 
 // table entry (high words) of particle j from the global table
@@ -201,21 +217,18 @@ __device__ __forceinline__ c64 tab64_entry(const double* __restrict__ tab, int64
 
 // gradient partials in FP64: gpart[(q * D + a) * N + j]
 template <int D>
-__global__ void __launch_bounds__(kThreads) k_grad64(const Span* __restrict__ runs,
-                                                     const int32_t* __restrict__ chunk_begin,
-                                                     const double* __restrict__ tab, const double* __restrict__ csw,
-                                                     int64_t N, int R1, int64_t M, double* __restrict__ gpart,
-                                                     const int* __restrict__ active) {
-  if (active && *active == 0) return;
+__device__ __forceinline__ void grad64_body(const Span* __restrict__ runs, const int32_t* __restrict__ chunk_begin,
+                                            const double* __restrict__ tab, const double* __restrict__ csw,
+                                            int64_t N, int R1, int64_t M, double* __restrict__ gpart, int64_t pblock,
+                                            int q) {
   __shared__ double s_g[kWaves][D][64];
   const int tid = threadIdx.x, lane = tid & 63;
   // the wave index is uniform across the wave: in a scalar register the run
   // bounds, the run records and the per-wavevector (vC, vS) become scalar loads
   // and the wavevector loop is a scalar loop
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t j = pblock * 64 + lane;
   const int64_t jj = j < N ? j : N - 1;
-  const int q = blockIdx.y;
   const int r0 = chunk_begin[kWaves * q + wave], r1 = chunk_begin[kWaves * q + wave + 1];
   const c64 z = tab64_entry(tab, N, R1, D - 1, 1, jj);
   double g[D];
@@ -252,14 +265,20 @@ __global__ void __launch_bounds__(kThreads) k_grad64(const Span* __restrict__ ru
   }
 }
 
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_grad64(const Span* __restrict__ runs,
+                                                     const int32_t* __restrict__ chunk_begin,
+                                                     const double* __restrict__ tab, const double* __restrict__ csw,
+                                                     int64_t N, int R1, int64_t M, double* __restrict__ gpart,
+                                                     const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  grad64_body<D>(runs, chunk_begin, tab, csw, N, R1, M, gpart, blockIdx.x, blockIdx.y);
+}
+
 // sum the Q FP64 partials in order, scale by 4 pi / L (and by L with times_L),
 // store in the dd layout with zero low words
-__global__ void __launch_bounds__(kThreads) k_grad_combine64(const double* __restrict__ gpart, int Q, int d,
-                                                             int64_t N, double L, int times_L,
-                                                             double* __restrict__ grad,
-                                                             const int* __restrict__ active) {
-  if (active && *active == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+__device__ __forceinline__ void gcomb64_body(const double* __restrict__ gpart, int Q, int d, int64_t N, double L,
+                                             bool times_L, double* __restrict__ grad, int64_t i) {
   const int64_t DN = (int64_t)d * N;
   if (i >= DN) return;
   double g = 0.0;
@@ -269,6 +288,55 @@ __global__ void __launch_bounds__(kThreads) k_grad_combine64(const double* __res
   if (times_L) g *= L;
   grad[i] = g;
   grad[DN + i] = 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads) k_grad_combine64(const double* __restrict__ gpart, int Q, int d,
+                                                             int64_t N, double L, int times_L,
+                                                             double* __restrict__ grad,
+                                                             const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  gcomb64_body(gpart, Q, d, N, L, times_L != 0, grad, (int64_t)blockIdx.x * kThreads + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// batched FP64 launches (the FP64 stage of staged quenches in a batch): the
+// same bodies over the blocks of many configurations, as in the double-double
+// batched kernels
+// ---------------------------------------------------------------------------
+template <int D, int PT>
+__global__ void __launch_bounds__(kThreads) kb_nk64(const EvalSlot* __restrict__ es, const BUnit* __restrict__ units,
+                                                    int gate) {
+  extern __shared__ double lds[];
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  nk64_body<D, PT>(E.segs, E.nsegs, E.units[u.idx], E.tab, E.N, E.R1, E.part, E.M, E.so, lds);
+}
+
+__global__ void __launch_bounds__(kThreads) kb_combine64(const EvalSlot* __restrict__ es,
+                                                         const BUnit* __restrict__ units, int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  combine64_body(E.part, E.rows_of, E.k_of_slot, E.M, E.N, E.canon_of_lex, E.v, nullptr, E.csw, E.blk, u.idx);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) kb_grad64(const EvalSlot* __restrict__ es,
+                                                      const BUnit* __restrict__ units, int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  grad64_body<D>(E.runs, E.chunk_begin, E.tab, E.csw, E.N, E.R1, E.M, E.gpart, u.idx % E.pblocks,
+                 (int)(u.idx / E.pblocks));
+}
+
+__global__ void __launch_bounds__(kThreads) kb_gcomb64(const EvalSlot* __restrict__ es,
+                                                       const BUnit* __restrict__ units, int which, int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  gcomb64_body(E.gpart, E.Q, E.d, E.N, E.L, E.L != 1.0, E.grad[which], (int64_t)u.idx * kThreads + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,6 +396,52 @@ hipError_t launch_grad_combine64(const LaunchCfg& c, const double* gpart, double
   const int64_t DN = (int64_t)c.d * c.N;
   hipLaunchKernelGGL(k_grad_combine64, dim3((unsigned)((DN + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
                      gpart, c.Q, c.d, c.N, L, times_L ? 1 : 0, grad, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_nk64(int d, int pt, int R1max, const EvalSlot* es, const BUnit* units, int64_t n, int gate,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const dim3 g((unsigned)n), b(kThreads);
+#define SS_NK64(DD, P) \
+  hipLaunchKernelGGL((kb_nk64<DD, P>), g, b, (size_t)P * DD * R1max * 2 * sizeof(double), st, es, units, gate)
+  switch (d * 100 + pt) {
+    case 116: SS_NK64(1, 16); break;
+    case 104: SS_NK64(1, 4); break;
+    case 101: SS_NK64(1, 1); break;
+    case 216: SS_NK64(2, 16); break;
+    case 204: SS_NK64(2, 4); break;
+    case 201: SS_NK64(2, 1); break;
+    case 316: SS_NK64(3, 16); break;
+    case 304: SS_NK64(3, 4); break;
+    case 301: SS_NK64(3, 1); break;
+    case 416: SS_NK64(4, 16); break;
+    case 404: SS_NK64(4, 4); break;
+    default: SS_NK64(4, 1); break;
+  }
+#undef SS_NK64
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_combine64(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_combine64, dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_grad64(int d, const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  switch (d) {
+    case 1: hipLaunchKernelGGL((kb_grad64<1>), dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate); break;
+    case 2: hipLaunchKernelGGL((kb_grad64<2>), dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate); break;
+    case 3: hipLaunchKernelGGL((kb_grad64<3>), dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate); break;
+    default: hipLaunchKernelGGL((kb_grad64<4>), dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gcomb64(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
+                                hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_gcomb64, dim3((unsigned)n), dim3(kThreads), 0, st, es, units, which, gate);
   return hipGetLastError();
 }
 

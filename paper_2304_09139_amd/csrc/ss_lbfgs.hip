@@ -821,16 +821,22 @@ __global__ void __launch_bounds__(kThreads) kb_accept(const MinSlot* __restrict_
 
 __global__ void __launch_bounds__(64) kb_init(const MinSlot* __restrict__ ms, const int32_t* __restrict__ list) {
   const MinSlot& C = ms[list[blockIdx.x]];
-  init_body(C.S, C.P, 0);
+  init_body(C.S, C.P, C.keep);
 }
 
-// running word of each listed configuration, gathered for one copy to the host
+// status of each listed configuration, gathered for one copy to the host
 __global__ void __launch_bounds__(kThreads) kb_flags(const MinSlot* __restrict__ ms, const int32_t* __restrict__ list,
-                                                     int64_t n, int32_t* __restrict__ out) {
+                                                     int64_t n, SlotFlags* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   const int32_t s = list[i];
-  out[s] = ms[s].S->running;
+  const MinState& S = *ms[s].S;
+  SlotFlags f;
+  f.running = S.running;
+  f.status = S.status;
+  f.iter = S.iter;
+  f.evals = S.evals;
+  out[s] = f;
 }
 
 hipError_t launch_batch_dots(const MinSlot* ms, const BUnit* units, int64_t n, int mode, hipStream_t st) {
@@ -853,7 +859,7 @@ hipError_t launch_batch_init(const MinSlot* ms, const int32_t* list, int64_t n, 
   if (n > 0) hipLaunchKernelGGL(kb_init, dim3((unsigned)n), dim3(64), 0, st, ms, list);
   return hipGetLastError();
 }
-hipError_t launch_batch_flags(const MinSlot* ms, const int32_t* list, int64_t n, int32_t* out, hipStream_t st) {
+hipError_t launch_batch_flags(const MinSlot* ms, const int32_t* list, int64_t n, SlotFlags* out, hipStream_t st) {
   if (n > 0)
     hipLaunchKernelGGL(kb_flags, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, ms, list, n,
                        out);

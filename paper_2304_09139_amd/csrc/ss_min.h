@@ -100,6 +100,13 @@ struct MinSlot {
   int64_t neblk;
   int64_t nv;
   int32_t dot_blocks;
+  int32_t keep;  // the start keeps the kept (s, y) pairs (a change of precision)
+};
+
+// per-configuration status gathered for the host after every batched step
+struct SlotFlags {
+  int32_t running, status;
+  int64_t iter, evals;
 };
 
 }  // namespace ss

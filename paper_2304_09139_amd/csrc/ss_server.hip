@@ -93,6 +93,7 @@ struct Request {
   size_t off = 0, bytes = 0;
   void* pin = nullptr;  // pinned copy-out buffer: positions then MinState
   hipEvent_t done_ev = nullptr;
+  int64_t iters64 = 0, evals64 = 0;  // a staged quench's FP64 stage
 };
 
 struct InFlight {
@@ -129,11 +130,11 @@ struct ss_server {
   std::vector<std::shared_ptr<ss::Request>> copying;
   ss::EvalSlot* d_es = nullptr;
   ss::MinSlot* d_ms = nullptr;
-  int32_t* d_flags = nullptr;
+  ss::SlotFlags* d_flags = nullptr;
   int32_t* d_list = nullptr;
   ss::BUnit* d_units = nullptr;
   size_t units_cap = 0;
-  int32_t* h_flags = nullptr;  // pinned [kDepth][max_slots]
+  ss::SlotFlags* h_flags = nullptr;  // pinned [kDepth][max_slots]
   char* h_desc = nullptr;      // pinned [max_slots] x (EvalSlot, MinSlot) upload staging
 };
 
@@ -310,8 +311,8 @@ class Worker {
   int enqueue_tick() {
     W_HIP(launch_tick(S->ctx, dev(), L, st));
     const int q = (int)(tick % kDepth);
-    int32_t* hf = S->h_flags + (size_t)q * S->max_slots;
-    W_HIP(hipMemcpyAsync(hf, S->d_flags, sizeof(int32_t) * S->max_slots, hipMemcpyDeviceToHost, st));
+    SlotFlags* hf = S->h_flags + (size_t)q * S->max_slots;
+    W_HIP(hipMemcpyAsync(hf, S->d_flags, sizeof(SlotFlags) * S->max_slots, hipMemcpyDeviceToHost, st));
     W_HIP(hipEventRecord(ring[q], st));
     InFlight f{ring[q], q, {}};
     for (int s : S->active) f.listed.push_back({s, S->slot_gen[s]});
@@ -325,16 +326,46 @@ class Worker {
     InFlight f = std::move(inflight.front());
     inflight.pop_front();
     W_HIP(hipEventSynchronize(f.ev));
-    const int32_t* hf = S->h_flags + (size_t)f.q * S->max_slots;
+    const SlotFlags* hf = S->h_flags + (size_t)f.q * S->max_slots;
     bool changed = false;
+    std::vector<int> sw;
     for (auto& [s, gen] : f.listed) {
-      if (hf[s] != 0 || S->slot_gen[s] != gen || !S->slot_req[s]) continue;
+      if (hf[s].running != 0 || S->slot_gen[s] != gen || !S->slot_req[s]) continue;
       auto it = std::find(S->active.begin(), S->active.end(), s);
       if (it == S->active.end()) continue;
+      HostSlot& h = S->hs[s];
+      if (h.phase == 0 && h.opts.precision == 2 && hf[s].status != 3) {
+        // a staged quench's FP64 stage has stopped: double-double from here
+        if (std::find(sw.begin(), sw.end(), s) == sw.end()) {
+          S->slot_req[s]->iters64 = hf[s].iter;
+          S->slot_req[s]->evals64 = hf[s].evals;
+          sw.push_back(s);
+        }
+        continue;
+      }
       S->active.erase(it);
       changed = true;
       int rc = copy_out(s);
       if (rc) return rc;
+    }
+    if (!sw.empty()) {
+      for (int s : sw) {
+        HostSlot& h = S->hs[s];
+        h.phase = 1;
+        // flags of steps already in flight still show the stopped FP64 stage:
+        // a new generation makes them stale
+        S->slot_gen[s] += 1;
+        // the slot's pinned descriptor cell: its previous copy ran before this
+        // configuration's first step
+        MinSlot* ms = (MinSlot*)(S->h_desc + (size_t)s * (sizeof(EvalSlot) + sizeof(MinSlot)) + sizeof(EvalSlot));
+        ms->P = stage_params(h, S->slot_req[s]->iters64);
+        ms->keep = 1;
+        W_HIP(hipMemcpyAsync(S->d_ms + s, ms, sizeof(MinSlot), hipMemcpyHostToDevice, st));
+      }
+      int rc = upload_lists(sw);
+      if (rc) return rc;
+      W_HIP(launch_start(S->ctx, dev(), L, st));
+      changed = true;
     }
     if (changed && !S->active.empty()) return upload_lists(S->active);
     return SS_OK;
@@ -392,15 +423,16 @@ class Worker {
       {
         std::lock_guard<std::mutex> g(S->mu);
         r->res.status = ms.status;
-        r->res.iters = ms.iter;
-        r->res.evals = ms.evals;
-        r->res.grad_evals = ms.evals;
+        r->res.iters = ms.iter + r->iters64;
+        r->res.evals = ms.evals + r->evals64;
+        r->res.grad_evals = r->res.evals;
         r->res.phi[0] = ms.f[0];
         r->res.phi[1] = ms.f[1];
         r->res.smax[0] = ms.smax[0];
         r->res.smax[1] = ms.smax[1];
-        r->res.iters_fp64 = 0;
-        r->res.evals_fp64 = 0;
+        const bool all64 = r->opts.precision == 1;
+        r->res.iters_fp64 = all64 ? ms.iter : r->iters64;
+        r->res.evals_fp64 = all64 ? ms.evals : r->evals64;
         r->res.seconds = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
         r->state = 3;
         S->cv.notify_all();
@@ -452,8 +484,8 @@ int check_request(ss_ctx* ctx, const ss_request* q, ss_problem* p) {
     ctx->last_error = "served requests take vkind 0 or 1";
     return SS_EINVAL;
   }
-  if (!min_opts_valid(&q->opts) || q->opts.precision != 0 || q->opts.method != 0) {
-    ctx->last_error = "invalid minimiser options (served quenches use precision 0, method 0)";
+  if (!min_opts_valid(&q->opts) || q->opts.method != 0) {
+    ctx->last_error = "invalid minimiser options (served quenches use L-BFGS, method 0)";
     return SS_EINVAL;
   }
   if (!(q->L > 0.0) || !isfinite(q->L)) {
@@ -490,10 +522,10 @@ extern "C" int ss_server_start(ss_ctx* ctx, void* arena_dev, size_t arena_bytes,
   bool ok = hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) == hipSuccess &&
             hipMalloc(&S->d_es, sizeof(EvalSlot) * max_slots) == hipSuccess &&
             hipMalloc(&S->d_ms, sizeof(MinSlot) * max_slots) == hipSuccess &&
-            hipMalloc(&S->d_flags, sizeof(int32_t) * max_slots) == hipSuccess &&
+            hipMalloc(&S->d_flags, sizeof(SlotFlags) * max_slots) == hipSuccess &&
             hipMalloc(&S->d_list, sizeof(int32_t) * max_slots) == hipSuccess &&
-            hipMemset(S->d_flags, 0, sizeof(int32_t) * max_slots) == hipSuccess &&
-            hipHostMalloc((void**)&S->h_flags, sizeof(int32_t) * max_slots * kDepth, hipHostMallocDefault) ==
+            hipMemset(S->d_flags, 0, sizeof(SlotFlags) * max_slots) == hipSuccess &&
+            hipHostMalloc((void**)&S->h_flags, sizeof(SlotFlags) * max_slots * kDepth, hipHostMallocDefault) ==
                 hipSuccess &&
             hipHostMalloc((void**)&S->h_desc, (sizeof(EvalSlot) + sizeof(MinSlot)) * max_slots,
                           hipHostMallocDefault) == hipSuccess;

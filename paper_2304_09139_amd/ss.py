@@ -151,6 +151,17 @@ def _stream(device):
 STATUS = {0: "converged", 1: "stalled", 2: "max_iter", 3: "numeric"}
 
 
+def _min_opts(opts: dict) -> MinOpts:
+    """MinOpts from the defaults updated by opts (precision and method by name or number)."""
+    o = dict(DEFAULT_MIN_OPTS)
+    o.update(opts)
+    if isinstance(o["precision"], str):
+        o["precision"] = PRECISION[o["precision"]]
+    if isinstance(o["method"], str):
+        o["method"] = METHOD[o["method"]]
+    return MinOpts(**o)
+
+
 def _result(r) -> dict:
     return dict(status=STATUS.get(r.status, str(r.status)), iters=r.iters, evals=r.evals, grad_evals=r.grad_evals,
                 phi=(r.phi[0], r.phi[1]), smax=(r.smax[0], r.smax[1]), seconds=r.seconds,
@@ -280,13 +291,7 @@ class Context:
     def minimize(self, w: Workload, n: torch.Tensor, v: torch.Tensor | None, pos: torch.Tensor,
                  **opts) -> dict:
         """L-BFGS quench of pos (updated in place, [2, d, N]) on the device."""
-        base = dict(DEFAULT_MIN_OPTS)
-        base.update(opts)
-        if isinstance(base["precision"], str):
-            base["precision"] = PRECISION[base["precision"]]
-        if isinstance(base["method"], str):
-            base["method"] = METHOD[base["method"]]
-        mo = MinOpts(**base)
+        mo = _min_opts(opts)
         res = MinResult()
         ws = self.workspace(w, 1)
         p = w.problem()
@@ -312,7 +317,7 @@ class Context:
     def _batch_args(works, opts_list):
         n = len(works)
         probs = (Problem * n)(*[w.problem() for w in works])
-        mos = (MinOpts * n)(*[MinOpts(**o) for o in opts_list])
+        mos = (MinOpts * n)(*[_min_opts(o) for o in opts_list])
         return probs, mos
 
     def batch_workspace_size(self, works: list[Workload], opts_list: list[dict]) -> int:
@@ -363,12 +368,10 @@ class Context:
         """Queue a quench of host positions pos (float64 [2, d, N]); returns its ticket."""
         import numpy as np
 
-        o = dict(DEFAULT_MIN_OPTS)
-        o.update(opts)
         p = np.ascontiguousarray(pos, dtype=np.float64)
         if p.shape != (2, w.d, w.N):
             raise ValueError("positions must be [2, d, N]")
-        req = Request(w.d, w.N, w.R2, w.L, w.vkind, p.ctypes.data, MinOpts(**o))
+        req = Request(w.d, w.N, w.R2, w.L, w.vkind, p.ctypes.data, _min_opts(opts))
         t = ctypes.c_uint64()
         self._chk(lib().ss_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "ss_submit")
         self._served = getattr(self, "_served", {})

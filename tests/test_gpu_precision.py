@@ -171,6 +171,3 @@ def test_precision_option_errors(ctx):
         with pytest.raises(ss.SSError) as e:
             ctx.minimize(w, n, None, dev(pos), **bad)
         assert e.value.code == ss.SS_EINVAL
-    with pytest.raises(ss.SSError) as e:
-        ctx.minimize_batch([w], [dev(pos)], opts=dict(precision=2))
-    assert e.value.code == ss.SS_EINVAL

@@ -94,6 +94,41 @@ def test_served_quenches_reach_floor(ctx):
         ctx.server_stop()
 
 
+def test_served_staged_equals_batch(ctx):
+    """Staged requests switch to double-double inside the server on their own:
+    served mixed with double-double requests, each result equals the batch of
+    one bit for bit and reaches the floor."""
+    items = [make(s) for s in SPECS[:4]]
+    kinds = [dict(precision="staged"), dict(precision="dd"), dict(precision="staged"), dict(precision="staged")]
+    ref = []
+    for (w, pos), o in zip(items, kinds):
+        x = torch.from_numpy(pos).cuda()
+        v = ctx.weights(w, ctx.wavevectors(w.d, w.R2)) if w.vkind else None
+        r = ctx.minimize_batch([w], [x], [v], opts=dict(o, s_floor=FLOOR))[0]
+        ref.append((r, x.cpu().numpy()))
+    ctx.server_start(1 << 30, max_slots=8)
+    try:
+        tickets = {}
+        for i in [2, 0, 3, 1]:
+            tickets[i] = ctx.submit(items[i][0], items[i][1], s_floor=FLOOR, **kinds[i])
+            time.sleep(0.005)
+        for i, t in tickets.items():
+            r, xs = wait(ctx, t)
+            rb, xb = ref[i]
+            assert np.array_equal(xs, xb), SPECS[i]
+            for key in ("phi", "smax", "iters", "evals", "iters_fp64", "evals_fp64", "status"):
+                assert r[key] == rb[key], (SPECS[i], key, r[key], rb[key])
+            assert r["status"] == "converged", (SPECS[i], r)
+            if kinds[i]["precision"] == "staged":
+                assert 0 < r["iters_fp64"] < r["iters"], (SPECS[i], r)
+            w = items[i][0]
+            n = O.wavevectors(w.d, w.R2)
+            v = O.weights(n, w.R2, 1) if w.vkind else None
+            assert O.energy_from_nk(w.N, v, O.nk(n, xs)).smax[0] <= FLOOR * (1 + 1e-6), SPECS[i]
+    finally:
+        ctx.server_stop()
+
+
 def test_small_arena_admission(ctx):
     """An arena that holds about one configuration at a time still serves all
     requests, one after another; a request larger than the arena fails alone."""
@@ -124,7 +159,7 @@ def test_serving_errors(ctx):
         with pytest.raises(ss.SSError) as e:
             ctx.server_start(1 << 20, max_slots=2)
         assert e.value.code == ss.SS_ESTATE
-        for bad in (dict(history=0), dict(precision=2)):
+        for bad in (dict(history=0), dict(method=1), dict(precision=3)):
             with pytest.raises(ss.SSError) as e:
                 ctx.submit(w, pos, **bad)
             assert e.value.code == ss.SS_EINVAL
