@@ -155,7 +155,7 @@ def main():
     ap.add_argument("--progress", type=float, default=0.0,
                     help="seconds between the library's progress lines on stderr (0: none)")
     ap.add_argument("--no-staged", action="store_true",
-                    help="skip the staged-precision quenches of the same starts")
+                    help="skip the staged-precision quenches of the same starts (single and batched workloads)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched workloads: skip timing the same configurations one at a time")
     ap.add_argument("--mp-report", action="store_true",
@@ -366,7 +366,7 @@ def bench_batch(args, wl):
     steps = args.steps if args.steps_set else 2
     starts = [[torch.from_numpy(inputs.config_positions(wl["cfg_id"], w.d, w.N, 1000 * r + i)).cuda()
                for i, w in enumerate(works)] for r in range(args.warmup + steps)]
-    opts = dict(s_floor=FLOOR)
+    opts = dict(s_floor=FLOOR, precision=args.precision)
     need = ctx.batch_workspace_size(works, [dict(ss.DEFAULT_MIN_OPTS, **opts)] * count)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
@@ -383,8 +383,32 @@ def bench_batch(args, wl):
     elapsed = time.perf_counter() - t0
     launches, gms, gpairs = ctx.profile_read("grad", reset=True, work=True)
     ctx.profile(False)
-    pairs = sum(w.M * w.N * r["evals"] for w, r in zip(works * steps, results))
+    # double-double pairs (the metric); FP64 evaluations of staged runs apart
+    pairs = sum(w.M * w.N * (r["evals"] - r["evals_fp64"]) for w, r in zip(works * steps, results))
+    pairs64 = sum(w.M * w.N * r["evals_fp64"] for w, r in zip(works * steps, results))
     converged = sum(1 for r in results if r["status"] == "converged")
+    staged = None
+    if args.precision == "dd" and not args.no_staged:
+        # the last step's batch again with staged precision (FP64 descent, each
+        # configuration switching to double-double on its own), same floor
+        xs = [torch.from_numpy(inputs.config_positions(wl["cfg_id"], w.d, w.N, 1000 * (args.warmup + steps - 1) + i))
+              .cuda() for i, w in enumerate(works)]
+        sopts = dict(opts, precision="staged")
+        wss = torch.empty(ctx.batch_workspace_size(works, [dict(ss.DEFAULT_MIN_OPTS, **sopts)] * count),
+                          dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sres = ctx.minimize_batch(works, xs, opts=sopts, ws=wss)
+        torch.cuda.synchronize()
+        st_el = time.perf_counter() - t1
+        st_conv = sum(1 for r in sres if r["status"] == "converged")
+        dd_last = sum(1 for r in results[-count:] if r["status"] == "converged") / (elapsed / steps)
+        staged = {"configs_per_s": st_conv / st_el, "converged": f"{st_conv}/{count}",
+                  "smax_worst": max(r["smax"][0] for r in sres),
+                  "iters_mean": sum(r["iters"] for r in sres) / count,
+                  "iters_fp64_mean": sum(r["iters_fp64"] for r in sres) / count,
+                  "speedup_configs_per_s": (st_conv / st_el) / dd_last}
+        del wss
     seq_conv, seq_elapsed = 0, float("nan")
     if not args.no_sequential:
         # one at a time (first step's starts again, fresh copies), timed once
@@ -411,13 +435,16 @@ def bench_batch(args, wl):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "dd",
+        "dtype": {"dd": "dd", "staged": "f64 then dd", "fp64": "f64"}[args.precision],
         "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
         "config": {"workload": f"batched L-BFGS quenches to S_max <= {FLOOR:g}: {count} configurations, "
-                               f"d in {{2,3}}, N log-uniform in [500, 5000], chi in {{0.2, 0.35, 0.45}}, v(k)=1",
-                   "configs": count, "s_floor": FLOOR, "parallelism": "single GPU"},
+                               f"d in {{2,3}}, N log-uniform in [500, 5000], chi in {{0.2, 0.35, 0.45}}, v(k)=1"
+                               + ("" if args.precision == "dd" else f", {args.precision} precision"),
+                   "configs": count, "s_floor": FLOOR, "precision": args.precision, "parallelism": "single GPU"},
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{len(results)}",
+        "fp64_pairs_per_s": pairs64 / elapsed,
+        "staged_precision": staged,
         "smax_worst": max(r["smax"][0] for r in results),
         "one_at_a_time": None if args.no_sequential else {
             "configs_per_s": seq_conv / seq_elapsed, "seconds": seq_elapsed, "converged": f"{seq_conv}/{count}"},
@@ -469,7 +496,7 @@ def bench_serve(args, wl):
         while len(done) < count:
             now = time.perf_counter() - t0
             while i < count and times[i] <= now:
-                tickets.append(ctx.submit(works[i], starts[i], s_floor=FLOOR))
+                tickets.append(ctx.submit(works[i], starts[i], s_floor=FLOOR, precision=args.precision))
                 i += 1
             for k, t in enumerate(tickets):
                 if k not in done:
@@ -502,12 +529,12 @@ def bench_serve(args, wl):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for w, n, x in zip(works, ns, xs):
-            r = ctx.minimize(w, n, None, x, s_floor=FLOOR)
+            r = ctx.minimize(w, n, None, x, s_floor=FLOOR, precision=args.precision)
             seq_conv += r["status"] == "converged"
         torch.cuda.synchronize()
         seq_s = time.perf_counter() - t1
     lat = np.array([r["seconds"] for r in opened])
-    pairs = sum(w.M * w.N * r["evals"] for w, r in zip(works, opened))
+    pairs = sum(w.M * w.N * (r["evals"] - r["evals_fp64"]) for w, r in zip(works, opened))
     conv = sum(1 for r in opened if r["status"] == "converged")
     out = {
         "metric": "dd particle-wavevector pairs/s (Phi+grad) and configs/s at stated max S(k) floor",
@@ -520,12 +547,13 @@ def bench_serve(args, wl):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "dd",
+        "dtype": {"dd": "dd", "staged": "f64 then dd", "fp64": "f64"}[args.precision],
         "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
         "config": {"workload": f"{count} served L-BFGS quenches to S_max <= {FLOOR:g}, d in {{2,3}}, "
                                f"N log-uniform in [{n_min}, {n_max}], chi uniform in [0.1, 0.49], Poisson "
-                               f"arrivals at 0.7 x capacity", "requests": count, "s_floor": FLOOR,
-                   "parallelism": "single GPU"},
+                               f"arrivals at 0.7 x capacity"
+                               + ("" if args.precision == "dd" else f", {args.precision} precision"),
+                   "requests": count, "s_floor": FLOOR, "precision": args.precision, "parallelism": "single GPU"},
         "configs_per_s": conv / open_s,
         "converged": f"{conv}/{count}",
         "capacity_configs_per_s": cap,
