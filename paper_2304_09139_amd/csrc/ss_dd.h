@@ -210,37 +210,42 @@ __device__ __forceinline__ dd phase_of(double m, double uh, double ul) {
   return t;
 }
 
-// sin and cos of a small dd angle x (|x| <= pi/16) by the nested Taylor form
-// sin x = x (1 - x^2/(2.3) (1 - x^2/(4.5) (1 - ...))) through x^19 and
-// cos x = 1 - x^2/(1.2) (1 - x^2/(3.4) (1 - ...)) through x^20.
-__device__ __forceinline__ void sincos_small(dd x, dd& s, dd& c) {
-  dd x2 = dd_mul(x, x);
-  dd ps{1.0, 0.0};
+// sin and cos of two small dd angles x0, x1 (|x| <= pi/16) by the nested
+// Taylor form sin x = x (1 - x^2/(2.3) (1 - x^2/(4.5) (1 - ...))) through x^19
+// and cos x = 1 - x^2/(1.2) (1 - x^2/(3.4) (1 - ...)) through x^20.  The four
+// recurrences share one loop so that their dependent chains interleave.
+__device__ __forceinline__ void sincos_small2(dd x0, dd x1, dd& s0, dd& c0, dd& s1, dd& c1) {
+  const dd a2 = dd_mul(x0, x0), b2 = dd_mul(x1, x1);
+  dd ps0{1.0, 0.0}, ps1{1.0, 0.0}, pc0{1.0, 0.0}, pc1{1.0, 0.0};
 #pragma unroll 1
-  for (int k = 9; k >= 1; --k) {  // factors (2k)(2k+1)
-    dd t = dd_div_d(dd_mul(x2, ps), (double)((2 * k) * (2 * k + 1)));
-    ps = dd_sub(dd{1.0, 0.0}, t);
+  for (int k = 10; k >= 1; --k) {
+    if (k <= 9) {  // sine factors (2k)(2k+1), k = 9 .. 1
+      const double fs = (double)((2 * k) * (2 * k + 1));
+      ps0 = dd_sub(dd{1.0, 0.0}, dd_div_d(dd_mul(a2, ps0), fs));
+      ps1 = dd_sub(dd{1.0, 0.0}, dd_div_d(dd_mul(b2, ps1), fs));
+    }
+    const double fc = (double)((2 * k - 1) * (2 * k));  // cosine factors, k = 10 .. 1
+    pc0 = dd_sub(dd{1.0, 0.0}, dd_div_d(dd_mul(a2, pc0), fc));
+    pc1 = dd_sub(dd{1.0, 0.0}, dd_div_d(dd_mul(b2, pc1), fc));
   }
-  s = dd_mul(x, ps);
-  dd pc{1.0, 0.0};
-#pragma unroll 1
-  for (int k = 10; k >= 1; --k) {  // factors (2k-1)(2k)
-    dd t = dd_div_d(dd_mul(x2, pc), (double)((2 * k - 1) * (2 * k)));
-    pc = dd_sub(dd{1.0, 0.0}, t);
-  }
-  c = pc;
+  s0 = dd_mul(x0, ps0);
+  s1 = dd_mul(x1, ps1);
+  c0 = pc0;
+  c1 = pc1;
 }
 
-// (cos 2 pi t, sin 2 pi t) for t in [-1/2, 1/2]: exact quarter-turn reduction,
-// then the angle is quartered, the small-angle series evaluated, and the angle
-// doubled twice (sin 2y = 2 sin y cos y, cos 2y = 1 - 2 sin^2 y).
-__device__ __forceinline__ cdd expi2pi(dd t) {
-  double q = __builtin_rint(4.0 * t.h);
-  dd r = dd_norm(t.h - 0.25 * q, t.l);  // exact by Sterbenz
-  dd th = dd_mul(two_pi_dd(), r);
-  dd y{0.25 * th.h, 0.25 * th.l};
-  dd s, c;
-  sincos_small(y, s, c);
+// quarter-turn reduction of t in [-1/2, 1/2]: t = q/4 + r exactly (Sterbenz),
+// and the quartered angle y = 2 pi r / 4
+__device__ __forceinline__ dd quarter_angle(dd t, double& q) {
+  q = __builtin_rint(4.0 * t.h);
+  const dd r = dd_norm(t.h - 0.25 * q, t.l);
+  const dd th = dd_mul(two_pi_dd(), r);
+  return dd{0.25 * th.h, 0.25 * th.l};
+}
+
+// the angle doubled twice (sin 2y = 2 sin y cos y, cos 2y = 1 - 2 sin^2 y), then
+// the quarter turns q restored
+__device__ __forceinline__ cdd unquarter(dd s, dd c, double q) {
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     dd s2 = dd_mul(s, c);
@@ -249,18 +254,23 @@ __device__ __forceinline__ cdd expi2pi(dd t) {
     c = dd_sub(dd{1.0, 0.0}, dd{2.0 * ss.h, 2.0 * ss.l});
     s = s2;
   }
-  int qi = ((int)q) & 3;
-  cdd z;
-  if (qi == 0) {
-    z = cdd{c.h, c.l, s.h, s.l};
-  } else if (qi == 1) {
-    z = cdd{-s.h, -s.l, c.h, c.l};
-  } else if (qi == 2) {
-    z = cdd{-c.h, -c.l, -s.h, -s.l};
-  } else {
-    z = cdd{s.h, s.l, -c.h, -c.l};
-  }
-  return z;
+  const int qi = ((int)q) & 3;
+  if (qi == 0) return cdd{c.h, c.l, s.h, s.l};
+  if (qi == 1) return cdd{-s.h, -s.l, c.h, c.l};
+  if (qi == 2) return cdd{-c.h, -c.l, -s.h, -s.l};
+  return cdd{s.h, s.l, -c.h, -c.l};
+}
+
+// (cos 2 pi t, sin 2 pi t) for two phases t0, t1 in [-1/2, 1/2]: exact
+// quarter-turn reduction, the small-angle series on the quartered angle, and
+// two angle doublings
+__device__ __forceinline__ void expi2pi2(dd t0, dd t1, cdd& z0, cdd& z1) {
+  double q0, q1;
+  const dd y0 = quarter_angle(t0, q0), y1 = quarter_angle(t1, q1);
+  dd s0, c0, s1, c1;
+  sincos_small2(y0, y1, s0, c0, s1, c1);
+  z0 = unquarter(s0, c0, q0);
+  z1 = unquarter(s1, c1, q1);
 }
 
 }  // namespace ss

@@ -92,7 +92,7 @@ struct LaunchCfg {
 constexpr int kThreads = 256;     // threads per block
 constexpr int kWaves = 4;         // waves per block
 constexpr int kNkPieces = 256;    // run pieces per n(k) block (one per lane)
-constexpr int kTabRun = 8;        // phase-table exponents per thread (one sin/cos pair each)
+constexpr int kTabRun = 16;       // phase-table exponents per thread (one sin/cos pair each)
 constexpr int kCombK = 32;        // wavevectors per block of the partial combine
 constexpr int kXcds = 8;          // accelerator complex dies (one L2 each); workgroups are dealt round-robin
 constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)

@@ -50,8 +50,8 @@ __device__ __forceinline__ void table_body(const double* __restrict__ pos, int d
   const int a = (int)(ag / groups);
   const double uh = pos[(int64_t)a * N + j];
   const double ul = pos[(int64_t)(d + a) * N + j];
-  cdd w = expi2pi(phase_of((double)m0, uh, ul));
-  const cdd z = expi2pi(phase_of(1.0, uh, ul));
+  cdd w, z;
+  expi2pi2(phase_of((double)m0, uh, ul), phase_of(1.0, uh, ul), w, z);
   for (int t = 0; t < kTabRun && m0 + t < R1; ++t) {
     if (t > 0) w = cmul(w, z);
     double rh, rl, ih, il;
@@ -398,7 +398,7 @@ __device__ __forceinline__ void grad_body(const Span* __restrict__ runs, const i
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads) k_grad(const Span* __restrict__ runs,
+__global__ void __launch_bounds__(kThreads, 5) k_grad(const Span* __restrict__ runs,
                                                    const int32_t* __restrict__ chunk_begin,
                                                    const double* __restrict__ tab, const double* __restrict__ csw,
                                                    int64_t N, int R1, int64_t M, double* __restrict__ gpart, int Q,
@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(kThreads) kb_table(const EvalSlot* __restrict_
 }
 
 template <int D, int PT>
-__global__ void __launch_bounds__(kThreads) kb_nk(const EvalSlot* __restrict__ es, const BUnit* __restrict__ units,
+__global__ void __launch_bounds__(kThreads, 3) kb_nk(const EvalSlot* __restrict__ es, const BUnit* __restrict__ units,
                                                   int gate) {
   extern __shared__ double lds[];  // [PT][D][R1][4], sized for the largest R1 of the launch
   const BUnit u = units[blockIdx.x];

@@ -67,27 +67,24 @@ __device__ __forceinline__ const double* vec_of(const VecSet& V, int code) {
 __device__ __forceinline__ dd vload(const double* p, int64_t nv, int64_t i) { return dd{p[i], p[nv + i]}; }
 
 // ---------------------------------------------------------------------------
-// the direction (run by the one block that finishes the direction products; rows live on
-// lanes i < k of wave 0).  Compact form with H0 = gamma I:
+// the direction (run by the one block that finishes the direction products, on
+// its LDS copy of the state; wave 0 works, row i on lane i < k).  Compact form
+// with H0 = gamma I:
 //   H g = gamma g + S top - gamma Y z,  R z = u,  R^T top = D z + gamma (Y^T Y z - w)
 // with u = S^T g, w = Y^T g, R the upper triangle of S^T Y and D its diagonal.
-// The triangular solves run column by column, rows held in registers.
+// The triangular solves run column by column; the loops run over the k kept
+// pairs only (short code: the kernel is a single block, so its time is mostly
+// instruction fetch when unrolled over the maximum history).
 // ---------------------------------------------------------------------------
 __device__ void direction_logic(MinState& S, const MinParams& P, int i) {
+  if (i >= 64) return;
   const int k = S.k;
   const dd gg = ld(S.dir_dots[2 * k]);
   const dd gmax = ld(S.dir_dots[2 * k + 1]);
   bool use_sd = (k == 0);
   dd gp{0.0, 0.0};
   if (!use_sd) {
-    dd rowR[kMaxHistory], colR[kMaxHistory], rowYY[kMaxHistory];
     const bool mine = i < k;
-#pragma unroll
-    for (int j = 0; j < kMaxHistory; ++j) {
-      rowR[j] = (mine && j < k) ? ld(S.SY[i][j]) : dd{0.0, 0.0};
-      colR[j] = (mine && j < k) ? ld(S.SY[j][i]) : dd{0.0, 0.0};
-      rowYY[j] = (mine && j < k) ? ld(S.YY[i][j]) : dd{0.0, 0.0};
-    }
     const dd u = mine ? ld(S.dir_dots[i]) : dd{0.0, 0.0};
     const dd w = mine ? ld(S.dir_dots[k + i]) : dd{0.0, 0.0};
     const dd gamma = dd_div(ld(S.SY[k - 1][k - 1]), ld(S.YY[k - 1][k - 1]));
@@ -95,31 +92,28 @@ __device__ void direction_logic(MinState& S, const MinParams& P, int i) {
     const dd rdiag = dd_div(dd{1.0, 0.0}, diag);  // all lanes at once, off the serial chain
     // back substitution R z = u (rows i < j updated with z_j)
     dd acc = u, zi{0.0, 0.0};
-#pragma unroll
-    for (int j = kMaxHistory - 1; j >= 0; --j) {
-      if (j < k) {
-        if (i == j) zi = dd_mul(acc, rdiag);
-        const dd zj = shfl_dd(zi, j);
-        if (i < j) acc = dd_sub(acc, dd_mul(rowR[j], zj));
-      }
+#pragma unroll 1
+    for (int j = k - 1; j >= 0; --j) {
+      if (i == j) zi = dd_mul(acc, rdiag);
+      const dd zj = shfl_dd(zi, j);
+      if (i < j) acc = dd_sub(acc, dd_mul(ld(S.SY[i][j]), zj));
     }
     // rhs_i = D_i z_i + gamma (sum_j YY_ij z_j - w_i)
     dd t{0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < kMaxHistory; ++j) {
-      if (j < k) t = dd_add(t, dd_mul(rowYY[j], shfl_dd(zi, j)));
+#pragma unroll 1
+    for (int j = 0; j < k; ++j) {
+      const dd zj = shfl_dd(zi, j);
+      if (mine) t = dd_add(t, dd_mul(ld(S.YY[i][j]), zj));
     }
     const dd rhs = dd_add(dd_mul(diag, zi), dd_mul(gamma, dd_sub(t, w)));
     // forward substitution R^T top = rhs (rows i > j updated with top_j)
     dd topi{0.0, 0.0};
     acc = rhs;
-#pragma unroll
-    for (int j = 0; j < kMaxHistory; ++j) {
-      if (j < k) {
-        if (i == j) topi = dd_mul(acc, rdiag);
-        const dd tj = shfl_dd(topi, j);
-        if (i > j) acc = dd_sub(acc, dd_mul(colR[j], tj));
-      }
+#pragma unroll 1
+    for (int j = 0; j < k; ++j) {
+      if (i == j) topi = dd_mul(acc, rdiag);
+      const dd tj = shfl_dd(topi, j);
+      if (i > j && mine) acc = dd_sub(acc, dd_mul(ld(S.SY[j][i]), tj));
     }
     const dd cs = dd_neg(topi);       // on S[slot_i]
     const dd cy = dd_mul(gamma, zi);  // on Y[slot_i]
@@ -131,12 +125,10 @@ __device__ void direction_logic(MinState& S, const MinParams& P, int i) {
     }
     // g.p = sum coef * (vector . g) in a fixed order
     gp = dd_mul(dd_neg(gamma), gg);
-#pragma unroll
-    for (int j = 0; j < kMaxHistory; ++j) {
-      if (j < k) {
-        gp = dd_add(gp, dd_mul(shfl_dd(cs, j), ld(S.dir_dots[j])));
-        gp = dd_add(gp, dd_mul(shfl_dd(cy, j), ld(S.dir_dots[k + j])));
-      }
+#pragma unroll 1
+    for (int j = 0; j < k; ++j) {
+      gp = dd_add(gp, dd_mul(shfl_dd(cs, j), ld(S.dir_dots[j])));
+      gp = dd_add(gp, dd_mul(shfl_dd(cy, j), ld(S.dir_dots[k + j])));
     }
     if (i == 0) {
       st(S.coef[0], dd_neg(gamma));
@@ -380,22 +372,18 @@ __device__ void decide_logic(MinState& S, const MinParams& P, int i) {
     const bool mine = i < k;
     const dd colsy = mine ? ld(S.trial_dots[2 + i]) : dd{0.0, 0.0};
     const dd colyy = mine ? ld(S.trial_dots[2 + k + i]) : dd{0.0, 0.0};
-    dd rowsy[kMaxHistory], rowyy[kMaxHistory];
     if (first) {
-#pragma unroll
-      for (int j = 0; j < kMaxHistory; ++j) {
-        rowsy[j] = (mine && j < k) ? ld(S.SY[i][j]) : dd{0.0, 0.0};
-        rowyy[j] = (mine && j < k) ? ld(S.YY[i][j]) : dd{0.0, 0.0};
-      }
-    }
-    __syncthreads();
-    if (first && i >= 1 && mine) {
-#pragma unroll
-      for (int j = 1; j < kMaxHistory; ++j) {
-        if (j < k) {
-          st(S.SY[i - 1][j - 1], rowsy[j]);
-          st(S.YY[i - 1][j - 1], rowyy[j]);
-        }
+      // shift both matrices up and left by one: thread (r, c) moves element
+      // (r, c), 1 <= r, c < k, to (r - 1, c - 1)
+      static_assert(kMaxHistory * kMaxHistory <= kThreads, "one thread per matrix element");
+      const int r = i / kMaxHistory, c = i % kMaxHistory;
+      const bool mv = i < kMaxHistory * kMaxHistory && r >= 1 && c >= 1 && r < k && c < k;
+      const dd esy = mv ? ld(S.SY[r][c]) : dd{0.0, 0.0};
+      const dd eyy = mv ? ld(S.YY[r][c]) : dd{0.0, 0.0};
+      __syncthreads();
+      if (mv) {
+        st(S.SY[r - 1][c - 1], esy);
+        st(S.YY[r - 1][c - 1], eyy);
       }
     }
     __syncthreads();
@@ -519,13 +507,24 @@ __global__ void __launch_bounds__(kThreads) k_dots(VecSet V, MinState* S_, int m
 // one block: each product's range partials summed in range order (kSubs
 // sub-ranges in parallel, then the sub-range sums in order), then the
 // direction (mode 0) or the Armijo decision (mode 1)
+// The block works on a copy of the state in LDS: one parallel load of the whole
+// state instead of the chain of dependent global loads that its decisions make,
+// and one parallel store of it at the end.
 __device__ __forceinline__ void dots_final_body(MinState* S_, const MinParams& P, int mode, int G,
                                                 const double* __restrict__ partial, const double* __restrict__ eblk,
                                                 int64_t neblk) {
-  MinState& S = *S_;
+  static_assert(sizeof(MinState) % sizeof(double) == 0, "state copied as 8-byte words");
+  constexpr int kWords = (int)(sizeof(MinState) / sizeof(double));
+  __shared__ MinState S;
+  const int tid = threadIdx.x;
+  {
+    const double* src = reinterpret_cast<const double*>(S_);
+    double* dst = reinterpret_cast<double*>(&S);
+    for (int w = tid; w < kWords; w += kThreads) dst[w] = src[w];
+  }
+  __syncthreads();
   if (!S.running) return;
   if (mode == 0 && S.phase != 0) return;
-  const int tid = threadIdx.x;
   if (mode == 1) {
     // the trial's Phi and S_max from the per-block partials of the energy pass
     dd phi, sm;
@@ -571,6 +570,12 @@ __device__ __forceinline__ void dots_final_body(MinState* S_, const MinParams& P
   __syncthreads();  // the products written above are read by other threads below
   if (mode == 0) direction_logic(S, P, tid);
   else decide_logic(S, P, tid);
+  __syncthreads();
+  {
+    const double* src = reinterpret_cast<const double*>(&S);
+    double* dst = reinterpret_cast<double*>(S_);
+    for (int w = tid; w < kWords; w += kThreads) dst[w] = src[w];
+  }
 }
 
 __global__ void __launch_bounds__(kThreads) k_dots_final(MinState* S_, MinParams P, int mode, int G,
