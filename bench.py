@@ -61,24 +61,51 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, workload: str) -> float | None:
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when there is none or it was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.txt")
+def read_profile(name: str) -> dict | None:
+    """key: value lines of a committed rocprofv3 counter summary, or None when
+    there is none or it was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line:
+            if ":" in line and not line.startswith("#"):
                 key, val = line.split(":", 1)
                 rec[key.strip()] = val.strip()
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
+    return rec
+
+
+def read_traffic(kernel: str, workload: str) -> float | None:
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, calibrated on a copy)."""
+    rec = read_profile(f"{kernel}_{workload}_counters.txt")
     try:
-        return float(rec["hbm_bytes_per_launch"])
+        return float(rec["hbm_bytes_per_launch"]) if rec else None
     except (KeyError, ValueError):
         return None
+
+
+def read_fp64_flops(kernel: str, workload: str) -> float | None:
+    """FP64 floating-point operations per launch with an FMA counted as two, from
+    the SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 wave-instruction counts (x 64 lanes)."""
+    rec = read_profile(f"{kernel}_{workload}_valu.txt")
+    try:
+        return 64.0 * (float(rec["add_f64"]) + float(rec["mul_f64"]) + 2.0 * float(rec["fma_f64"])) if rec else None
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def mp_error_report(ctx, w, n, v, pos, count=6, seed=7):
@@ -141,6 +168,7 @@ def cpu_baseline(d, N, chi, cfg_id):
     t2 = time.perf_counter() - t
     per_pair = t1 / (k_s * N) + t2 / (j_s * M)     # seconds per pair, both passes
     return {"value": 1.0 / per_pair, "unit": "dd pairs/s (Phi+grad)", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"n~ pass over {k_s} of {M} wavevectors x all {N} particles ({t1:.1f} s) and gradient "
                       f"pass over {j_s} of {N} particles x all {M} wavevectors ({t2:.1f} s), seed 0"}
 
@@ -270,6 +298,17 @@ def main():
     prof["table"] = ctx.profile_read("table", reset=True)
     ctx.profile_read("grad", reset=True)
     ctx.profile(False)
+    # one Phi + gradient evaluation (ss_energy_grad) timed with HIP events on its
+    # stream: the median of 50 after 5 warm-ups
+    for _ in range(5):
+        ctx.energy_grad(w, n, v, starts[0], grad=True, out=out_e)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+    for a, b in ev:
+        a.record()
+        ctx.energy_grad(w, n, v, starts[0], grad=True, out=out_e)
+        b.record()
+    torch.cuda.synchronize()
+    t_eval = sorted(a.elapsed_time(b) for a, b in ev)[25] * 1e-3
 
     evals = sum(r["evals"] for r in results)
     evals_fp64 = sum(r["evals_fp64"] for r in results)
@@ -285,6 +324,7 @@ def main():
         avg_s = ms / max(launches, 1) * 1e-3
     achieved = OPS_PER_PAIR["grad"] * w.M * N / avg_s if launches else 0.0
     traffic = read_traffic("k_grad", args.workload)
+    flops = read_fp64_flops("k_grad", args.workload)
     nk_l, nk_ms = prof["nk"]
     out = {
         "metric": "dd particle-wavevector pairs/s (Phi+grad) and configs/s at stated max S(k) floor",
@@ -322,6 +362,10 @@ def main():
         "path_frac_of_fp64_peak": value * (OPS_PER_PAIR["nk"] + OPS_PER_PAIR["grad"]) / PEAK_FP64_OPS,
         "nk_pass_frac_of_fp64_peak": (OPS_PER_PAIR["nk"] * w.M * N / (nk_ms / max(nk_l, 1) * 1e-3)) / PEAK_FP64_OPS
         if nk_l else None,
+        # one evaluation on its own: M N / t_eval, and the paper's two-sums count 2 M N / t_eval
+        "eval_pairs_per_s": w.M * N / t_eval,
+        "eval_two_sums_per_s": 2 * w.M * N / t_eval,
+        "eval_ms_median": t_eval * 1e3,
         "eval_ms_nk_pass": nk_ms / max(nk_l, 1),
         "eval_ms_grad_pass": ms / max(launches, 1),
         "eval_ms_table": prof["table"][1] / max(prof["table"][0], 1),
@@ -336,6 +380,11 @@ def main():
             "op_count": f"{OPS_PER_PAIR['grad']} FP64 add/mul/fma per pair (each counted once) x M N pairs "
                         f"per launch; peak = 256 CU x 64 lanes x 2.4 GHz",
             "launches": launches,
+            # the same launches in floating-point operations with an FMA counted as
+            # two (SQ counters of the committed profile) against the 78.6 T peak
+            "fma_weighted": None if flops is None else {
+                "achieved_tflops": flops / avg_s / 1e12, "peak_tflops": 78.6,
+                "frac": flops / avg_s / 78.6e12, "flops_per_launch": flops},
         },
     }
     if args.precision == "staged" or args.mp_report:
