@@ -31,9 +31,9 @@ FLOOR = 1e-40
 # FP64 operations (add, mul, fma each counted once) per particle-wavevector pair
 # in the inner loops, counted from the kernel source: the n~(k) pass does one
 # lazy complex dd product (2 x 16) and two lazy dd accumulations (2 x 8); the
-# gradient pass does the complex product (32), v (S c - C s) (16), two lazy
-# accumulations (2 x 8), n_d q (3) and the exponent step (1).
-OPS_PER_PAIR = {"nk": 48, "grad": 68}
+# gradient pass does the complex product (32), v (S c - C s) (16) and two lazy
+# accumulations (2 x 8: the sum of q and the sum of its prefix sums).
+OPS_PER_PAIR = {"nk": 48, "grad": 64}
 # MI355X: 256 CUs x 64 FP64 lanes x 2.4 GHz, one FP64 VALU op per lane per clock
 PEAK_FP64_OPS = 256 * 64 * 2.4e9
 WORKLOADS = {
@@ -357,7 +357,7 @@ def main():
         "evals_fp64_mean": evals_fp64 / len(results),
         "fp64_pairs_per_s": w.M * N * evals_fp64 / elapsed,
         "evals_mean": evals / len(results),
-        # the whole quench against the FP64 issue peak: 116 operations per pair
+        # the whole quench against the FP64 issue peak: 112 operations per pair
         # (both passes) at the measured pair rate, minimiser overhead included
         "path_frac_of_fp64_peak": value * (OPS_PER_PAIR["nk"] + OPS_PER_PAIR["grad"]) / PEAK_FP64_OPS,
         "nk_pass_frac_of_fp64_peak": (OPS_PER_PAIR["nk"] * w.M * N / (nk_ms / max(nk_l, 1) * 1e-3)) / PEAK_FP64_OPS

@@ -347,8 +347,10 @@ __device__ __forceinline__ void grad_body(const Span* __restrict__ runs, const i
     cdd w = tab_entry(tab, N, R1, D - 1, run.n[D - 1], jj);
 #pragma unroll
     for (int a = 0; a < D - 1; ++a) w = cmul(w, tab_entry(tab, N, R1, a, run.n[a], jj));
-    double q0h = 0.0, q0l = 0.0, qdh = 0.0, qdl = 0.0;
-    double nd = (double)run.n[D - 1];
+    // q_t = v (S c - C s) along the run; P = sum_t q_t and the sum of the prefix
+    // sums PP = sum_t P_t give sum_t (n0 + t) q_t = (n0 + len) P - PP without a
+    // product per pair
+    double q0h = 0.0, q0l = 0.0, pph = 0.0, ppl = 0.0;
     const double* cp = csw + run.k0;
 #pragma unroll 2
     for (int t = 0; t < run.len; ++t) {
@@ -356,15 +358,21 @@ __device__ __forceinline__ void grad_body(const Span* __restrict__ runs, const i
       double qs, qt;
       lazy_dot2m(Sh, Sl, w.rh, w.rl, Ch, Cl, w.ih, w.il, qs, qt);  // v (S c - C s)
       lazy_acc(q0h, q0l, qs, qt);
-      double p = nd * qs;
-      double e = __builtin_fma(nd, qs, -p);
-      e = __builtin_fma(nd, qt, e);
-      lazy_acc(qdh, qdl, p, e);
-      nd += 1.0;
+      lazy_acc(pph, ppl, q0h, q0l);
       w = cmul(w, z);
     }
     renorm(q0h, q0l);
-    renorm(qdh, qdl);
+    renorm(pph, ppl);
+    double qdh, qdl;
+    {
+      const double nl = (double)(run.n[D - 1] + run.len);
+      double p = nl * q0h;
+      double e = __builtin_fma(nl, q0h, -p);
+      e = __builtin_fma(nl, q0l, e);
+      const dd r = dd_sub(dd_norm(p, e), dd{pph, ppl});
+      qdh = r.h;
+      qdl = r.l;
+    }
 #pragma unroll
     for (int a = 0; a < D - 1; ++a) {
       const double na = (double)run.n[a];
