@@ -77,6 +77,11 @@ CASES = [
     ("d2_N1_single", 2, 1, 40, 0, 1.0, 6),
     ("d3_N3_R2_1", 3, 3, 1, 0, 1.0, 7),
     ("d3_N2500_chi0.45", 3, 2500, None, 0, 1.0, 8),
+    # large cutoffs (any K is a valid energy): particle tables of 4 and of 1
+    # particle per LDS tile in the n~ pass, long runs in the gradient pass
+    ("d2_N300_R2_5000_lds4", 2, 300, 5000, 0, 1.0, 9),
+    ("d3_N100_R2_1900_lds4_weighted", 3, 100, 1900, 1, 1.0, 10),
+    ("d2_N200_R2_70000_lds1", 2, 200, 70000, 0, 1.0, 12),
 ]
 
 
@@ -190,6 +195,14 @@ def test_invalid_arguments(ctx):
     rc = ss.lib().ss_energy_grad(ctx._h, ctypes.byref(p), ss._ptr(n), None, ss._ptr(pos), ss._ptr(phi), None,
                                  None, None, ss._ptr(small), 16, None)
     assert rc == ss.SS_EINVAL
+    # a cutoff whose particle table (d (R + 1) dd complex entries) exceeds the
+    # 64 KB LDS tile is rejected: d = 2, R = 1030
+    R2b = 1030 * 1030
+    wb = ss.Workload(2, 10, R2b, ss.count(2, R2b))
+    nb = ctx.wavevectors(2, R2b)
+    with pytest.raises(ss.SSError) as e:
+        ctx.energy_grad(wb, nb, None, dev(inputs.uniform_positions(2, 10, 3)))
+    assert e.value.code == ss.SS_EINVAL
 
 
 @pytest.mark.parametrize("d,N,chi,vkind,cfg,nk_samples,grad_samples",
