@@ -41,6 +41,10 @@ hipError_t enumerate(int d, int64_t R2, int R, hipStream_t st, Plan* pl);
 size_t minimize_extra_bytes(int64_t nv);
 int grad_blocks_per_cu(int d);
 int nk_blocks_per_cu(int d, int pt, int R1);
+int nk2_blocks_per_cu();
+hipError_t launch_nk2(const int32_t* tiles, int64_t ntiles, const int32_t* lexinfo, int R, const double* tab,
+                      int64_t N, int R1, int64_t chunk, int nrows, double* part, int64_t M, hipStream_t st,
+                      const int* active);
 }  // namespace ss
 
 using namespace ss;
@@ -180,6 +184,47 @@ int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
   SS_HIP(ctx, hipMemcpy(pl->segs, segs.data(), sizeof(Span) * segs.size(), hipMemcpyHostToDevice));
   pl->run_len_prefix.assign(runs.size() + 1, 0);
   for (size_t r = 0; r < runs.size(); ++r) pl->run_len_prefix[r + 1] = pl->run_len_prefix[r] + runs[r].len;
+  if (d == 2 && pl->R >= kNk2MinR) {
+    // rows n0 = 0 .. R of H: walk positions off .. off + hi - lo hold n1 = lo .. hi
+    const int R = pl->R;
+    std::vector<int32_t> info((size_t)3 * (R + 1), 0);
+    for (int n0 = 0; n0 <= R; ++n0) {
+      info[3 * n0] = 0;
+      info[3 * n0 + 1] = 1;
+      info[3 * n0 + 2] = 0;  // empty unless found below
+    }
+    for (int64_t k = 0; k < M; ++k) {
+      const int n0 = lex[2 * k], n1 = lex[2 * k + 1];
+      if (n0 < 0 || n0 > R) return set_err(ctx, SS_EHIP, "wavevector outside the half space");
+      if (k == 0 || lex[2 * (k - 1)] != n0) {
+        info[3 * n0] = (int32_t)k;
+        info[3 * n0 + 1] = n1;
+      } else if (n1 != lex[2 * (k - 1) + 1] + 1) {
+        return set_err(ctx, SS_EHIP, "rows of H are not intervals in walk order");
+      }
+      info[3 * n0 + 2] = n1;
+    }
+    std::vector<int32_t> tiles;
+    for (int a0 = 0; a0 <= R; a0 += 16)
+      for (int b0 = -R; b0 <= R; b0 += 16) {
+        bool meets = false;
+        for (int n0 = a0; n0 < a0 + 16 && n0 <= R && !meets; ++n0)
+          meets = info[3 * n0 + 1] <= info[3 * n0 + 2] && info[3 * n0 + 1] <= b0 + 15 && info[3 * n0 + 2] >= b0;
+        if (meets) {
+          tiles.push_back(a0);
+          tiles.push_back(b0);
+        }
+      }
+    std::vector<int32_t> ident((size_t)M);
+    for (int64_t k = 0; k < M; ++k) ident[k] = (int32_t)k;
+    pl->t2_ntiles = (int64_t)tiles.size() / 2;
+    SS_HIP(ctx, hipMalloc(&pl->t2_tiles, sizeof(int32_t) * tiles.size()));
+    SS_HIP(ctx, hipMalloc(&pl->t2_lexinfo, sizeof(int32_t) * info.size()));
+    SS_HIP(ctx, hipMalloc(&pl->t2_ident, sizeof(int32_t) * M));
+    SS_HIP(ctx, hipMemcpy(pl->t2_tiles, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice));
+    SS_HIP(ctx, hipMemcpy(pl->t2_lexinfo, info.data(), sizeof(int32_t) * info.size(), hipMemcpyHostToDevice));
+    SS_HIP(ctx, hipMemcpy(pl->t2_ident, ident.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
+  }
   ctx->plans[key] = pl;
   *out = pl;
   return SS_OK;
@@ -323,6 +368,30 @@ int nk_schedule_fixed(ss_ctx* ctx, Plan* pl, int64_t N, int pt, int64_t chunk, P
   return SS_OK;
 }
 
+// tiled d = 2 n(k) pass: the particles split into nrows chunks (multiples of 16)
+// so that tiles x nrows is about two rounds of resident blocks
+int nk2_schedule(ss_ctx* ctx, Plan* pl, int64_t N, Plan::Nk2Sched** out) {
+  auto it = pl->nk2_sched.find(N);
+  if (it != pl->nk2_sched.end()) {
+    *out = &it->second;
+    return SS_OK;
+  }
+  const int64_t target = 2 * (int64_t)num_cus(ctx) * nk2_blocks_per_cu();
+  int64_t nrows = std::max<int64_t>(1, (target + pl->t2_ntiles / 2) / std::max<int64_t>(1, pl->t2_ntiles));
+  nrows = std::min<int64_t>(nrows, std::min<int64_t>(kMaxNkRows, (N + 15) / 16));
+  int64_t chunk = (N + nrows - 1) / nrows;
+  chunk = ((chunk + 15) / 16) * 16;
+  Plan::Nk2Sched sc;
+  sc.chunk = chunk;
+  sc.nrows = (int)((N + chunk - 1) / chunk);
+  std::vector<int32_t> rows((size_t)pl->M, sc.nrows);
+  SS_HIP(ctx, hipMalloc(&sc.rows_of, sizeof(int32_t) * rows.size()));
+  SS_HIP(ctx, hipMemcpy(sc.rows_of, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice));
+  pl->nk2_sched[N] = sc;
+  *out = &pl->nk2_sched[N];
+  return SS_OK;
+}
+
 // launch shape and workspace layout; tile == nullptr: the single-launch shape
 // (grids sized to the device), else the batched shape of `tile`
 int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const TileSpec* tile = nullptr) {
@@ -344,6 +413,12 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const Til
     if (rc) return rc;
   }
   c->P = sc->rows;
+  if (!tile && pl->t2_ntiles > 0) {  // partial rows of the tiled d = 2 pass
+    Plan::Nk2Sched* s2 = nullptr;
+    int rc = nk2_schedule(ctx, pl, c->N, &s2);
+    if (rc) return rc;
+    c->P = std::max<int64_t>(c->P, s2->nrows);
+  }
   // gradient pass: blocks of 64 particles x Q chunks, each wave of a block on one
   // of kWaves sub-chunks of equal pair count
   const int64_t pblocks = (c->N + 63) / 64;
@@ -475,14 +550,26 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
   SS_HIP(ctx, timed(ctx, 2, st, (double)p->d * c.R1 * p->N,
                     [&] { return launch_table(pos, p->d, p->N, c.R1, tab, st, active); }));
   Plan::NkSched* sc = &pl->nk_sched.at(p->N);
-  SS_HIP(ctx, timed(ctx, 0, st, pairs, [&] {
-           return fp64 ? launch_nk64(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active)
-                       : launch_nk(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active);
-         }));
-  if (fp64)
-    SS_HIP(ctx, launch_nk_combine64(c, part, sc->rows_of, pl->k_of_slot, pl->canon_of_lex, v, nk, csw, blk, st, active));
-  else
-    SS_HIP(ctx, launch_nk_combine(c, part, sc->rows_of, pl->k_of_slot, pl->canon_of_lex, v, nk, csw, blk, st, active));
+  // d = 2 at large cutoffs: the tiled pass writes its partials by walk position
+  const auto t2 = pl->nk2_sched.find(p->N);
+  const bool tiled = !fp64 && pl->t2_ntiles > 0 && t2 != pl->nk2_sched.end() && t2->second.nrows <= c.P;
+  if (tiled) {
+    const Plan::Nk2Sched& s2 = t2->second;
+    SS_HIP(ctx, timed(ctx, 0, st, pairs, [&] {
+             return launch_nk2(pl->t2_tiles, pl->t2_ntiles, pl->t2_lexinfo, pl->R, tab, p->N, c.R1, s2.chunk, s2.nrows,
+                               part, p->M, st, active);
+           }));
+    SS_HIP(ctx, launch_nk_combine(c, part, s2.rows_of, pl->t2_ident, pl->canon_of_lex, v, nk, csw, blk, st, active));
+  } else {
+    SS_HIP(ctx, timed(ctx, 0, st, pairs, [&] {
+             return fp64 ? launch_nk64(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active)
+                         : launch_nk(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active);
+           }));
+    if (fp64)
+      SS_HIP(ctx, launch_nk_combine64(c, part, sc->rows_of, pl->k_of_slot, pl->canon_of_lex, v, nk, csw, blk, st, active));
+    else
+      SS_HIP(ctx, launch_nk_combine(c, part, sc->rows_of, pl->k_of_slot, pl->canon_of_lex, v, nk, csw, blk, st, active));
+  }
   if (phi) SS_HIP(ctx, launch_final(c, blk, phi, smax ? smax : scal + 2, kmax, st, active));
   if (grad) {
     int32_t* cb = nullptr;
@@ -542,6 +629,10 @@ int ss_destroy(ss_ctx* ctx) {
       hipFree(ns.second.units);
       hipFree(ns.second.rows_of);
     }
+    hipFree(pl->t2_tiles);
+    hipFree(pl->t2_lexinfo);
+    hipFree(pl->t2_ident);
+    for (auto& ns : pl->nk2_sched) hipFree(ns.second.rows_of);
     delete pl;
   }
   for (auto& v : ctx->prof.ev)

@@ -65,6 +65,17 @@ struct Plan {
   };
   std::map<int64_t, NkSched> nk_sched;           // N -> n(k) pass schedule (single launches)
   std::map<std::pair<int64_t, int64_t>, NkSched> nk_fixed;  // (N, chunk) -> fixed-chunk schedule (batches)
+  // d = 2 with R >= kNk2MinR: the tiled n(k) pass of single launches (k_nk2)
+  int32_t* t2_tiles = nullptr;    // device [t2_ntiles][2]: (a0, b0) of the 16 x 16 tiles that meet H
+  int64_t t2_ntiles = 0;
+  int32_t* t2_lexinfo = nullptr;  // device [R + 1][3]: walk position of (n0, lo), lo, hi
+  int32_t* t2_ident = nullptr;    // device [M]: slot = walk position
+  struct Nk2Sched {
+    int64_t chunk = 0;            // particles per partial row
+    int nrows = 0;
+    int32_t* rows_of = nullptr;   // device [M], all nrows
+  };
+  std::map<int64_t, Nk2Sched> nk2_sched;         // N -> schedule
 };
 
 // Tile shape of the batched launches for one configuration: particles per n(k)
@@ -98,6 +109,7 @@ constexpr int kXcds = 8;          // accelerator complex dies (one L2 each); wor
 constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)
 constexpr int64_t kDefaultGradK = 1024;
 constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks per n(k) piece block
+constexpr int kNk2MinR = 48;                 // d = 2 cutoffs from which single launches use k_nk2
 
 }  // namespace ss
 

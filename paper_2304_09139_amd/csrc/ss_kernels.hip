@@ -182,6 +182,81 @@ __global__ void __launch_bounds__(kThreads, 3) k_nk(const Span* __restrict__ seg
 }
 
 // ---------------------------------------------------------------------------
+// n~(k) partial sums for d = 2 at large cutoffs, as a product of two table
+// slices.  With the phase table, exp(2 pi i n.u_j) = z0_j^{n0} z1_j^{n1}, so a
+// 16 x 16 tile of wavevectors (n0 in [a0, a0 + 16), n1 in [b0, b0 + 16)) over a
+// particle chunk needs only 16 + 16 table rows per particle: the block stages
+// them for 16 particles at a time (coalesced: 16 consecutive particles per row
+// and component) and thread (i0, i1) adds z0^{n0} z1^{n1} -- one complex
+// product per pair, no walk and no prefix products.  Thread t takes
+// i0 = t / 16, i1 = t % 16; threads whose (n0, n1) is not in H idle.
+// lexinfo[3 n0 + (0, 1, 2)] = walk position of (n0, lo), lo, hi: the n1 of H in
+// row n0 are lo .. hi.  part[(row * 4 + c) * M + walk position].
+// ---------------------------------------------------------------------------
+constexpr int kT2 = 16;                 // tile side and particles per staged chunk
+constexpr int kT2Pitch = kT2 * 4 + 2;   // doubles per staged particle (pad: no bank conflicts)
+
+__global__ void __launch_bounds__(kThreads) k_nk2(const int32_t* __restrict__ tiles,
+                                                  const int32_t* __restrict__ lexinfo, int R,
+                                                  const double* __restrict__ tab, int64_t N, int R1, int64_t chunk,
+                                                  int nrows, double* __restrict__ part, int64_t M,
+                                                  const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  __shared__ double s0[kT2 * kT2Pitch], s1[kT2 * kT2Pitch];  // [particle][row][re.h, re.l, im.h, im.l]
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x / nrows, row = blockIdx.x % nrows;
+  const int a0 = tiles[2 * tile], b0 = tiles[2 * tile + 1];
+  const int i0 = tid / kT2, i1 = tid % kT2;
+  const int n0 = a0 + i0, n1 = b0 + i1;
+  int64_t pos = -1;
+  if (n0 <= R) {
+    const int off = lexinfo[3 * n0], lo = lexinfo[3 * n0 + 1], hi = lexinfo[3 * n0 + 2];
+    if (n1 >= lo && n1 <= hi) pos = off + (n1 - lo);
+  }
+  const bool mine = pos >= 0;
+  const bool neg = n1 < 0;
+  double crh = 0.0, crl = 0.0, cih = 0.0, cil = 0.0;
+  const int64_t j0 = (int64_t)row * chunk;
+  const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
+  for (int64_t tj = j0; tj < j1; tj += kT2) {
+    const int np = (int)((j1 - tj) < kT2 ? (j1 - tj) : kT2);
+    __syncthreads();
+    // 2 slices x 16 rows x 4 components x 16 particles, particle fastest
+#pragma unroll
+    for (int q = 0; q < (2 * kT2 * 4 * kT2) / kThreads; ++q) {
+      const int idx = tid + kThreads * q;
+      const int p = idx % kT2, c = (idx / kT2) % 4, r = (idx / (4 * kT2)) % kT2, ax = idx / (4 * kT2 * kT2);
+      const int m = ax == 0 ? a0 + r : (b0 + r < 0 ? -(b0 + r) : b0 + r);
+      double val = 0.0;
+      if (p < np && m <= R) val = tab[((int64_t)(ax * R1 + m) * 4 + c) * N + tj + p];
+      (ax == 0 ? s0 : s1)[p * kT2Pitch + r * 4 + c] = val;
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll 4
+      for (int p = 0; p < np; ++p) {
+        const double* e0 = s0 + p * kT2Pitch + i0 * 4;
+        const double* e1 = s1 + p * kT2Pitch + i1 * 4;
+        cdd z1{e1[0], e1[1], e1[2], e1[3]};
+        if (neg) z1 = cconj(z1);
+        const cdd w = cmul(cdd{e0[0], e0[1], e0[2], e0[3]}, z1);
+        lazy_acc(crh, crl, w.rh, w.rl);
+        lazy_acc(cih, cil, w.ih, w.il);
+      }
+      renorm(crh, crl);
+      renorm(cih, cil);
+    }
+  }
+  if (mine) {
+    double* out = part + (int64_t)row * 4 * M;
+    out[pos] = crh;
+    out[M + pos] = crl;
+    out[2 * M + pos] = cih;
+    out[3 * M + pos] = cil;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // combine the P chunk partials per wavevector (fixed order, accurate dd sums);
 // write n~ in canonical order, (v C, v S) in walk order, and per-block Phi and
 // S_max partials.  Block b covers slots b kCombK .. (b + 1) kCombK - 1 (reads of
@@ -691,6 +766,21 @@ hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const N
     case 3: return launch_nk_d<3>(c, segs, nseg, units, nunits, tab, part, so, st, active);
     default: return launch_nk_d<4>(c, segs, nseg, units, nunits, tab, part, so, st, active);
   }
+}
+
+hipError_t launch_nk2(const int32_t* tiles, int64_t ntiles, const int32_t* lexinfo, int R, const double* tab,
+                      int64_t N, int R1, int64_t chunk, int nrows, double* part, int64_t M, hipStream_t st,
+                      const int* active) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nk2, dim3((unsigned)(ntiles * nrows)), dim3(kThreads), 0, st, tiles, lexinfo, R, tab, N, R1,
+                     chunk, nrows, part, M, active);
+  return hipGetLastError();
+}
+
+int nk2_blocks_per_cu() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_nk2, kThreads, 0) != hipSuccess) b = 1;
+  return b > 0 ? b : 1;
 }
 
 hipError_t launch_nk_combine(const LaunchCfg& c, const double* part, const int32_t* rows_of,
