@@ -184,7 +184,7 @@ int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
   SS_HIP(ctx, hipMemcpy(pl->segs, segs.data(), sizeof(Span) * segs.size(), hipMemcpyHostToDevice));
   pl->run_len_prefix.assign(runs.size() + 1, 0);
   for (size_t r = 0; r < runs.size(); ++r) pl->run_len_prefix[r + 1] = pl->run_len_prefix[r] + runs[r].len;
-  if (d == 2 && pl->R >= kNk2MinR) {
+  if (d == 2 && pl->R >= kNk2SmallR) {
     // rows n0 = 0 .. R of H: walk positions off .. off + hi - lo hold n1 = lo .. hi
     const int R = pl->R;
     std::vector<int32_t> info((size_t)3 * (R + 1), 0);
@@ -413,7 +413,7 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const Til
     if (rc) return rc;
   }
   c->P = sc->rows;
-  if (!tile && pl->t2_ntiles > 0) {  // partial rows of the tiled d = 2 pass
+  if (!tile && pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, c->N)) {  // partial rows of the tiled d = 2 pass
     Plan::Nk2Sched* s2 = nullptr;
     int rc = nk2_schedule(ctx, pl, c->N, &s2);
     if (rc) return rc;
@@ -552,7 +552,8 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
   Plan::NkSched* sc = &pl->nk_sched.at(p->N);
   // d = 2 at large cutoffs: the tiled pass writes its partials by walk position
   const auto t2 = pl->nk2_sched.find(p->N);
-  const bool tiled = !fp64 && pl->t2_ntiles > 0 && t2 != pl->nk2_sched.end() && t2->second.nrows <= c.P;
+  const bool tiled = !fp64 && pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, p->N) && t2 != pl->nk2_sched.end() &&
+                     t2->second.nrows <= c.P;
   if (tiled) {
     const Plan::Nk2Sched& s2 = t2->second;
     SS_HIP(ctx, timed(ctx, 0, st, pairs, [&] {

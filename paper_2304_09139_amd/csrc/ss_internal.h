@@ -65,7 +65,7 @@ struct Plan {
   };
   std::map<int64_t, NkSched> nk_sched;           // N -> n(k) pass schedule (single launches)
   std::map<std::pair<int64_t, int64_t>, NkSched> nk_fixed;  // (N, chunk) -> fixed-chunk schedule (batches)
-  // d = 2 with R >= kNk2MinR: the tiled n(k) pass of single launches (k_nk2)
+  // d = 2 with R >= kNk2SmallR: the tiled n(k) pass of single launches (k_nk2)
   int32_t* t2_tiles = nullptr;    // device [t2_ntiles][2]: (a0, b0) of the 16 x 16 tiles that meet H
   int64_t t2_ntiles = 0;
   int32_t* t2_lexinfo = nullptr;  // device [R + 1][3]: walk position of (n0, lo), lo, hi
@@ -109,7 +109,15 @@ constexpr int kXcds = 8;          // accelerator complex dies (one L2 each); wor
 constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)
 constexpr int64_t kDefaultGradK = 1024;
 constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks per n(k) piece block
-constexpr int kNk2MinR = 48;                 // d = 2 cutoffs from which single launches use k_nk2
+// d = 2 single launches use the tiled n(k) pass (k_nk2) from R = kNk2MinR on, and
+// from R = kNk2SmallR on when N <= kNk2SmallN (measured: the piece walk is faster
+// only in between, e.g. N = 8000 at R = 45)
+constexpr int kNk2MinR = 48;
+constexpr int kNk2SmallR = 16;
+constexpr int64_t kNk2SmallN = 2500;
+inline bool use_nk2(int d, int R, int64_t N) {
+  return d == 2 && (R >= kNk2MinR || (R >= kNk2SmallR && N <= kNk2SmallN));
+}
 
 }  // namespace ss
 
