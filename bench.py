@@ -50,6 +50,10 @@ WORKLOADS = {
     # the same stream shape at N log-uniform in [1e3, 1e5] (24 requests: the large
     # ones take seconds each)
     "serve24_d2-3_N1e3-1e5": dict(serve=24, stream_seed=8, cfg_id=7, n_min=1000, n_max=100000, arena_gb=96),
+    # the paper's production shape, one Phi + gradient evaluation at a time (a
+    # quench at this size takes hours): d = 2, N = 2e6, chi = 0.1 and 0.4
+    "d2_N2e6_chi0.1": dict(d=2, N=2_000_000, chi=0.1, cfg_id=9, evals_only=True),
+    "d2_N2e6_chi0.4": dict(d=2, N=2_000_000, chi=0.4, cfg_id=9, evals_only=True),
 }
 
 
@@ -209,6 +213,8 @@ def main():
     from paper_2304_09139_amd import inputs, ss
 
     wl = WORKLOADS[args.workload]
+    if wl.get("evals_only"):
+        return bench_evals(args, wl)
     if "batch" in wl:
         return bench_batch(args, wl)
     if "serve" in wl:
@@ -392,6 +398,56 @@ def main():
         out["error_vs_mp256_final"] = mp_error_report(ctx, w, n, v, starts[args.warmup + args.steps - 1])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, N, chi, wl["cfg_id"])
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_evals(args, wl):
+    """Single Phi + gradient evaluations (ss_energy_grad) of one configuration,
+    timed with HIP events on the call's stream after one warm-up evaluation."""
+    import torch
+
+    from paper_2304_09139_amd import inputs, ss
+
+    d, N, chi = wl["d"], wl["N"], wl["chi"]
+    ctx = ss.Context(0)
+    w = ss.Workload.from_chi(d, N, chi)
+    n = ctx.wavevectors(d, w.R2)
+    x = torch.from_numpy(inputs.config_positions(wl["cfg_id"], d, N, 0)).cuda()
+    ws_bytes = ctx.workspace_size(w, 0)
+    out = ctx.energy_grad(w, n, None, x, grad=True)
+    torch.cuda.synchronize()
+    steps = args.steps if args.steps_set else 3
+    ctx.profile(True)
+    for k in ("table", "nk", "grad"):
+        ctx.profile_read(k, reset=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        ctx.energy_grad(w, n, None, x, grad=True, out=out)
+        b.record()
+        print(f"[bench] evaluation done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    prof = {k: ctx.profile_read(k, reset=True) for k in ("table", "nk", "grad")}
+    ctx.profile(False)
+    t = sorted(a.elapsed_time(b) for a, b in ev)[steps // 2] * 1e-3
+    pairs = w.M * N
+    out = {
+        "metric": "dd particle-wavevector pairs/s of one Phi + gradient evaluation",
+        "value": pairs / t, "unit": "pairs/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "dd",
+        "data": "synthetic (seeded uniform-random positions, the paper's Poisson initial condition)",
+        "config": {"workload": f"one Phi + gradient evaluation, d={d}, N={N}, chi={chi}, v(k)=1 (the paper's "
+                               f"production shape)", "d": d, "N": N, "chi": chi, "R2": w.R2, "M": w.M,
+                   "parallelism": "single GPU"},
+        "two_sums_per_s": 2 * pairs / t,
+        "workspace_gb": ws_bytes / 1e9,
+        "pass_ms": {k: v[1] / max(v[0], 1) for k, v in prof.items()},
+        "nk_pass_frac_of_fp64_peak": OPS_PER_PAIR["nk"] * pairs / (prof["nk"][1] / max(prof["nk"][0], 1) * 1e-3)
+        / PEAK_FP64_OPS,
+        "grad_pass_frac_of_fp64_peak": OPS_PER_PAIR["grad"] * pairs / (prof["grad"][1] / max(prof["grad"][0], 1)
+                                                                        * 1e-3) / PEAK_FP64_OPS,
+    }
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -1,0 +1,51 @@
+"""One Phi + gradient evaluation at the paper's production shape: d = 2,
+N = 2 x 10^6 particles, chi = 0.1 (R2 = 254626, M = 399996 wavevectors, 8 x 10^11
+pairs, a 65 GB phase table in HBM).
+
+The oracle cannot sum every pair at this size in a test's time, so the checks
+are: n~ at sampled wavevectors (the smallest |k|, the outermost shell and
+others) against the oracle to |dC|, |dS| <= 1e-26 N; translation invariance of
+the gradient (sum_j dPhi/dr_j = 0, the total force on the system); and two
+evaluations giving the same bits.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2304_09139_amd import inputs, ss
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-26
+
+
+def test_d2_N2e6_chi01_evaluation():
+    d, N, chi = 2, 2_000_000, 0.1
+    ctx = ss.Context(0)
+    try:
+        R2, M = ss.cutoff(d, N, chi)
+        assert (R2, M) == (254626, 399996)
+        w = ss.Workload(d, N, R2, M)
+        n_t = ctx.wavevectors(d, R2)
+        pos = inputs.config_positions(9, d, N, 0)
+        x = torch.from_numpy(pos).cuda()
+        out = ctx.energy_grad(w, n_t, None, x, grad=True, nk=True)
+        got = {k: t.cpu().numpy() for k, t in out.items()}
+        again = ctx.energy_grad(w, n_t, None, x, grad=True, nk=True)
+        for k in got:
+            assert np.array_equal(again[k].cpu().numpy(), got[k]), k
+        n = n_t.cpu().numpy()
+        ks = np.array([0, 1, 7, M // 3, M // 2, M - 2, M - 1])
+        ref = O.nk(n[ks], pos)
+        dC = np.abs((got["nk"][0, ks] - ref[0]) + (got["nk"][1, ks] - ref[1]))
+        dS = np.abs((got["nk"][2, ks] - ref[2]) + (got["nk"][3, ks] - ref[3]))
+        assert dC.max() <= TOL * N and dS.max() <= TOL * N, (dC.max() / N, dS.max() / N)
+        g = got["grad"]
+        tot = np.abs(g[0].sum(axis=1) + g[1].sum(axis=1))
+        assert np.all(tot <= 1e-12 * np.abs(g[0]).sum(axis=1)), tot
+        print(f"d=2 N=2e6 chi=0.1: max|dn~|/N = {max(dC.max(), dS.max()) / N:.2e}, |sum_j g| = {tot}")
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
