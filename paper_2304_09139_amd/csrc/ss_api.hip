@@ -392,6 +392,27 @@ int nk2_schedule(ss_ctx* ctx, Plan* pl, int64_t N, Plan::Nk2Sched** out) {
   return SS_OK;
 }
 
+// fixed-chunk schedule of the tiled d = 2 pass in batches: partial rows of
+// `chunk` particles (rounded up to 16), a function of (N, chunk) only
+int nk2_schedule_fixed(ss_ctx* ctx, Plan* pl, int64_t N, int64_t chunk, Plan::Nk2Sched** out) {
+  chunk = std::max<int64_t>(16, ((chunk + 15) / 16) * 16);
+  const auto key = std::make_pair(N, chunk);
+  auto it = pl->nk2_fixed.find(key);
+  if (it != pl->nk2_fixed.end()) {
+    *out = &it->second;
+    return SS_OK;
+  }
+  Plan::Nk2Sched sc;
+  sc.chunk = chunk;
+  sc.nrows = (int)((N + chunk - 1) / chunk);
+  std::vector<int32_t> rows((size_t)pl->M, sc.nrows);
+  SS_HIP(ctx, hipMalloc(&sc.rows_of, sizeof(int32_t) * rows.size()));
+  SS_HIP(ctx, hipMemcpy(sc.rows_of, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice));
+  pl->nk2_fixed[key] = sc;
+  *out = &pl->nk2_fixed[key];
+  return SS_OK;
+}
+
 // launch shape and workspace layout; tile == nullptr: the single-launch shape
 // (grids sized to the device), else the batched shape of `tile`
 int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const TileSpec* tile = nullptr) {
@@ -413,9 +434,9 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const Til
     if (rc) return rc;
   }
   c->P = sc->rows;
-  if (!tile && pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, c->N)) {  // partial rows of the tiled d = 2 pass
+  if (pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, c->N, tile != nullptr)) {  // partial rows of the tiled d = 2 pass
     Plan::Nk2Sched* s2 = nullptr;
-    int rc = nk2_schedule(ctx, pl, c->N, &s2);
+    int rc = tile ? nk2_schedule_fixed(ctx, pl, c->N, tile->nk_chunk, &s2) : nk2_schedule(ctx, pl, c->N, &s2);
     if (rc) return rc;
     c->P = std::max<int64_t>(c->P, s2->nrows);
   }
@@ -476,7 +497,7 @@ TileSpec tile_for(ss_ctx* ctx, int d, int64_t N, int64_t M) {
 
 // the batched shape of a problem: plan, layout, n(k) schedule and gradient chunks
 int prepare_tiled(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg, Plan::NkSched** sc,
-                  int32_t** chunk_begin) {
+                  int32_t** chunk_begin, Plan::Nk2Sched** s2) {
   int rc = check_problem(ctx, p);
   if (rc) return rc;
   SS_HIP(ctx, hipSetDevice(ctx->device));
@@ -488,6 +509,11 @@ int prepare_tiled(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg, P
   if (rc) return rc;
   rc = nk_schedule_fixed(ctx, *pl, p->N, cfg->pt, t.nk_chunk, sc);
   if (rc) return rc;
+  *s2 = nullptr;
+  if ((*pl)->t2_ntiles > 0 && use_nk2(p->d, (*pl)->R, p->N, true)) {
+    rc = nk2_schedule_fixed(ctx, *pl, p->N, t.nk_chunk, s2);
+    if (rc) return rc;
+  }
   return chunk_bounds(ctx, *pl, cfg->Q * kWaves, chunk_begin);
 }
 
@@ -552,7 +578,7 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
   Plan::NkSched* sc = &pl->nk_sched.at(p->N);
   // d = 2 at large cutoffs: the tiled pass writes its partials by walk position
   const auto t2 = pl->nk2_sched.find(p->N);
-  const bool tiled = !fp64 && pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, p->N) && t2 != pl->nk2_sched.end() &&
+  const bool tiled = !fp64 && pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, p->N, false) && t2 != pl->nk2_sched.end() &&
                      t2->second.nrows <= c.P;
   if (tiled) {
     const Plan::Nk2Sched& s2 = t2->second;
@@ -634,6 +660,7 @@ int ss_destroy(ss_ctx* ctx) {
     hipFree(pl->t2_lexinfo);
     hipFree(pl->t2_ident);
     for (auto& ns : pl->nk2_sched) hipFree(ns.second.rows_of);
+    for (auto& ns : pl->nk2_fixed) hipFree(ns.second.rows_of);
     delete pl;
   }
   for (auto& v : ctx->prof.ev)

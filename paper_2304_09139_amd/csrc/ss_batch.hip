@@ -46,7 +46,7 @@ size_t min_bytes(int64_t nv, int m, int G) {
 }
 
 int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot* h) {
-  int rc = prepare_tiled(ctx, p, &h->pl, &h->c, &h->sc, &h->cb);
+  int rc = prepare_tiled(ctx, p, &h->pl, &h->c, &h->sc, &h->cb, &h->s2);
   if (rc) return rc;
   if (!min_opts_valid(op)) {
     ctx->last_error = "invalid minimiser options";
@@ -65,6 +65,7 @@ int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot
   const int groups = (h->c.R1 + kTabRun - 1) / kTabRun;
   h->n_table = ((int64_t)p->d * groups * p->N + kThreads - 1) / kThreads;
   h->n_nk = h->sc->nunits;
+  h->n_nk2 = h->s2 ? h->pl->t2_ntiles * h->s2->nrows : 0;
   h->n_comb = h->c.combine_blocks;
   h->n_grad = ((p->N + 63) / 64) * h->c.Q;
   h->n_gcomb = (h->nv + kThreads - 1) / kThreads;
@@ -73,6 +74,11 @@ int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot
   h->work = (double)p->M * (double)p->N;
   h->phase = op->precision == 0 ? 1 : 0;
   return SS_OK;
+}
+
+int64_t max_units(const HostSlot& h) {
+  const int64_t nk = std::max<int64_t>(h.n_nk, h.s2 ? h.n_nk2 : 0);
+  return h.n_table + nk + h.n_comb + h.n_grad + h.n_gcomb + h.n_dots + h.n_vec;
 }
 
 MinParams stage_params(const HostSlot& h, int64_t iters_done) {
@@ -109,12 +115,24 @@ void build_lists(const std::vector<HostSlot>& hs, std::vector<int> active, std::
   for (int ph = 1; ph >= 0; --ph) {
     auto& nkg = ph ? L.nk : L.nk64;
     auto& grg = ph ? L.grad : L.grad64;
-    // n(k) pass grouped by (d, LDS tile)
+    // n(k) pass grouped by (d, LDS tile); double-double evaluations of d = 2
+    // configurations with a tiled schedule form a group of their own (pt = 0)
+    auto tiled = [&](int s) { return ph == 1 && hs[s].s2 != nullptr; };
+    {
+      Lists::Group g{2, 0, 0, (int64_t)U.size(), 0, 0.0};
+      for (int s : active)
+        if (hs[s].phase == ph && tiled(s)) {
+          add(hs[s].n_nk2, s);
+          g.pairs += hs[s].work;
+        }
+      g.n = (int64_t)U.size() - g.off;
+      if (g.n > 0) nkg.push_back(g);
+    }
     for (int d = 1; d <= 4; ++d)
       for (int pt : {16, 4, 1}) {
         Lists::Group g{d, pt, 0, (int64_t)U.size(), 0, 0.0};
         for (int s : active)
-          if (hs[s].phase == ph && hs[s].prob.d == d && hs[s].c.pt == pt) {
+          if (hs[s].phase == ph && !tiled(s) && hs[s].prob.d == d && hs[s].c.pt == pt) {
             add(hs[s].n_nk, s);
             g.R1max = std::max(g.R1max, hs[s].c.R1);
             g.pairs += hs[s].work;
@@ -210,6 +228,16 @@ void fill_slot(const HostSlot& h, char* mem, double* x, const double* v, EvalSlo
   E->canon_of_lex = h.pl->canon_of_lex;
   E->v = h.prob.vkind == 0 ? nullptr : v;
   E->so = h.pl->slot_off;
+  if (h.s2) {
+    E->nk2 = 1;
+    E->R = h.pl->R;
+    E->t2_nrows = h.s2->nrows;
+    E->t2_chunk = h.s2->chunk;
+    E->t2_tiles = h.pl->t2_tiles;
+    E->t2_lexinfo = h.pl->t2_lexinfo;
+    E->t2_rows_of = h.s2->rows_of;
+    E->t2_ident = h.pl->t2_ident;
+  }
   E->tab = (double*)(mem + c.off_tab);
   E->part = (double*)(mem + c.off_part);
   E->csw = (double*)(mem + c.off_csw);
@@ -253,8 +281,10 @@ hipError_t launch_eval(ss_ctx* ctx, const DevArrays& D, const Lists& L, int whic
                        [&] { return launch_batch_table(D.es, D.units + L.table_off, L.table_n, which, gate, st); });
   if (e != hipSuccess) return e;
   for (const auto& g : L.nk) {
-    e = timed(ctx, 0, st, g.pairs,
-              [&] { return launch_batch_nk(g.d, g.pt, g.R1max, D.es, D.units + g.off, g.n, gate, st); });
+    e = timed(ctx, 0, st, g.pairs, [&] {
+      return g.pt == 0 ? launch_batch_nk2(D.es, D.units + g.off, g.n, gate, st)
+                       : launch_batch_nk(g.d, g.pt, g.R1max, D.es, D.units + g.off, g.n, gate, st);
+    });
     if (e != hipSuccess) return e;
   }
   e = launch_batch_combine(D.es, D.units + L.comb_off, L.comb_n, gate, st);
@@ -330,7 +360,11 @@ int setup_all(ss_ctx* ctx, int count, const ss_problem* probs, const ss_min_opts
     ctx->last_error = "batch too large for one launch";
     return SS_EINVAL;
   }
-  *ucap = (int64_t)U.size();
+  // a configuration's units depend on its evaluation precision (the tiled and
+  // the walked n(k) pass differ): room for the most any of them can take
+  int64_t cap = 0;
+  for (const HostSlot& h : hs) cap += max_units(h);
+  *ucap = std::max<int64_t>(cap, (int64_t)U.size());
   size_t hoff[6];
   header_offsets(count, *ucap, hoff);
   size_t t = hoff[5];
@@ -464,6 +498,11 @@ extern "C" int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs
   // launches that read the previous lists
   auto upload = [&](const std::vector<int>& active) {
     build_lists(hs, active, U, list, L);
+    if ((int64_t)U.size() > ucap) {
+      ctx->last_error = "batched work list larger than its buffer";
+      err = SS_EHIP;
+      return false;
+    }
     const int k = up_next;
     up_next = (up_next + 1) % kStages;
     if (up_pending[k] && !ok(hipEventSynchronize(ev_up[k]), "event sync")) return false;

@@ -13,7 +13,7 @@
 
 namespace ss {
 int prepare_tiled(ss_ctx* ctx, const ss_problem* p, Plan** pl, LaunchCfg* cfg, Plan::NkSched** sc,
-                  int32_t** chunk_begin);
+                  int32_t** chunk_begin, Plan::Nk2Sched** s2);
 TileSpec tile_for(ss_ctx* ctx, int d, int64_t N, int64_t M);
 bool min_opts_valid(const ss_min_opts* op);
 MinParams min_params(const ss_min_opts* op, const ss_problem* prob);
@@ -22,6 +22,7 @@ hipError_t launch_batch_table(const EvalSlot* es, const BUnit* units, int64_t n,
                               hipStream_t st);
 hipError_t launch_batch_nk(int d, int pt, int R1max, const EvalSlot* es, const BUnit* units, int64_t n, int gate,
                            hipStream_t st);
+hipError_t launch_batch_nk2(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
 hipError_t launch_batch_combine(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
 hipError_t launch_batch_final(const EvalSlot* es, const int32_t* list, int64_t n, hipStream_t st);
 hipError_t launch_batch_grad(int d, const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
@@ -49,12 +50,14 @@ struct HostSlot {
   Plan* pl = nullptr;
   LaunchCfg c{};
   Plan::NkSched* sc = nullptr;
+  Plan::Nk2Sched* s2 = nullptr;  // the tiled d = 2 pass of the double-double evaluations, or none
   int32_t* cb = nullptr;
   int64_t nv = 0;
   int m = 0, G = 0;
   size_t bytes = 0;  // workspace of this configuration (energy + minimiser)
   // unit counts of this configuration's grids
   int64_t n_table = 0, n_nk = 0, n_comb = 0, n_grad = 0, n_gcomb = 0, n_dots = 0, n_vec = 0;
+  int64_t n_nk2 = 0;  // tiles x rows of the tiled pass (dd evaluations when s2 is set)
   double work = 0.0;  // M N, for ordering
   int phase = 1;      // evaluation precision now: 0 FP64 (first stage or FP64 only), 1 double-double
 };
@@ -62,7 +65,7 @@ struct HostSlot {
 // offsets and counts of each batched launch inside the unit array
 struct Lists {
   struct Group {
-    int d, pt, R1max;
+    int d, pt, R1max;  // pt = 0: the tiled d = 2 pass
     int64_t off, n;
     double pairs;  // M N summed over the group's configurations
   };
@@ -94,6 +97,8 @@ void build_lists(const std::vector<HostSlot>& hs, std::vector<int> active, std::
 void fill_slot(const HostSlot& h, char* mem, double* x, const double* v, EvalSlot* E, MinSlot* C);
 // the minimiser parameters of a configuration's current stage
 MinParams stage_params(const HostSlot& h, int64_t iters_done);
+// the most units a configuration contributes to one tick's lists (either precision)
+int64_t max_units(const HostSlot& h);
 // the starting evaluation and tests of every listed configuration
 hipError_t launch_start(ss_ctx* ctx, const DevArrays& D, const Lists& L, hipStream_t st);
 // one minimiser step of every listed configuration, ending with the gather of

@@ -76,6 +76,7 @@ struct Plan {
     int32_t* rows_of = nullptr;   // device [M], all nrows
   };
   std::map<int64_t, Nk2Sched> nk2_sched;         // N -> schedule
+  std::map<std::pair<int64_t, int64_t>, Nk2Sched> nk2_fixed;  // (N, chunk) -> schedule (batches)
 };
 
 // Tile shape of the batched launches for one configuration: particles per n(k)
@@ -109,14 +110,16 @@ constexpr int kXcds = 8;          // accelerator complex dies (one L2 each); wor
 constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)
 constexpr int64_t kDefaultGradK = 1024;
 constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks per n(k) piece block
-// d = 2 single launches use the tiled n(k) pass (k_nk2) from R = kNk2MinR on, and
-// from R = kNk2SmallR on when N <= kNk2SmallN (measured: the piece walk is faster
-// only in between, e.g. N = 8000 at R = 45)
+// d = 2 evaluations use the tiled n(k) pass (k_nk2) from R = kNk2MinR on; single
+// launches also from R = kNk2SmallR on when N <= kNk2SmallN, where the piece
+// walk's grid is small (measured: the walk is faster in between, e.g. N = 8000 at
+// R = 45, and in batches below R = 48, where the grid is full anyway and the
+// tiles' idle lanes outside H cost more)
 constexpr int kNk2MinR = 48;
 constexpr int kNk2SmallR = 16;
 constexpr int64_t kNk2SmallN = 2500;
-inline bool use_nk2(int d, int R, int64_t N) {
-  return d == 2 && (R >= kNk2MinR || (R >= kNk2SmallR && N <= kNk2SmallN));
+inline bool use_nk2(int d, int R, int64_t N, bool batched) {
+  return d == 2 && (R >= kNk2MinR || (!batched && R >= kNk2SmallR && N <= kNk2SmallN));
 }
 
 }  // namespace ss

@@ -196,15 +196,11 @@ __global__ void __launch_bounds__(kThreads, 3) k_nk(const Span* __restrict__ seg
 constexpr int kT2 = 16;                 // tile side and particles per staged chunk
 constexpr int kT2Pitch = kT2 * 4 + 2;   // doubles per staged particle (pad: no bank conflicts)
 
-__global__ void __launch_bounds__(kThreads) k_nk2(const int32_t* __restrict__ tiles,
-                                                  const int32_t* __restrict__ lexinfo, int R,
-                                                  const double* __restrict__ tab, int64_t N, int R1, int64_t chunk,
-                                                  int nrows, double* __restrict__ part, int64_t M,
-                                                  const int* __restrict__ active) {
-  if (active && *active == 0) return;
+__device__ __forceinline__ void nk2_body(const int32_t* __restrict__ tiles, const int32_t* __restrict__ lexinfo,
+                                         int R, const double* __restrict__ tab, int64_t N, int R1, int64_t chunk,
+                                         int tile, int row, double* __restrict__ part, int64_t M) {
   __shared__ double s0[kT2 * kT2Pitch], s1[kT2 * kT2Pitch];  // [particle][row][re.h, re.l, im.h, im.l]
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x / nrows, row = blockIdx.x % nrows;
   const int a0 = tiles[2 * tile], b0 = tiles[2 * tile + 1];
   const int i0 = tid / kT2, i1 = tid % kT2;
   const int n0 = a0 + i0, n1 = b0 + i1;
@@ -254,6 +250,15 @@ __global__ void __launch_bounds__(kThreads) k_nk2(const int32_t* __restrict__ ti
     out[2 * M + pos] = cih;
     out[3 * M + pos] = cil;
   }
+}
+
+__global__ void __launch_bounds__(kThreads) k_nk2(const int32_t* __restrict__ tiles,
+                                                  const int32_t* __restrict__ lexinfo, int R,
+                                                  const double* __restrict__ tab, int64_t N, int R1, int64_t chunk,
+                                                  int nrows, double* __restrict__ part, int64_t M,
+                                                  const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  nk2_body(tiles, lexinfo, R, tab, N, R1, chunk, (int)(blockIdx.x / nrows), (int)(blockIdx.x % nrows), part, M);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,12 +554,24 @@ __global__ void __launch_bounds__(kThreads, 3) kb_nk(const EvalSlot* __restrict_
   nk_body<D, PT>(E.segs, E.nsegs, E.units[u.idx], E.tab, E.N, E.R1, E.part, E.M, E.so, lds);
 }
 
+// the tiled d = 2 pass (configurations with E.nk2): unit idx = tile * rows + row
+__global__ void __launch_bounds__(kThreads) kb_nk2(const EvalSlot* __restrict__ es, const BUnit* __restrict__ units,
+                                                   int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  nk2_body(E.t2_tiles, E.t2_lexinfo, E.R, E.tab, E.N, E.R1, E.t2_chunk, u.idx / E.t2_nrows, u.idx % E.t2_nrows,
+           E.part, E.M);
+}
+
+// double-double partials: of the tiled pass (by walk position) or of the piece walk
 __global__ void __launch_bounds__(kThreads) kb_combine(const EvalSlot* __restrict__ es,
                                                        const BUnit* __restrict__ units, int gate) {
   const BUnit u = units[blockIdx.x];
   const EvalSlot& E = es[u.slot];
   if (gate && *E.running == 0) return;
-  combine_body(E.part, E.rows_of, E.k_of_slot, E.M, E.N, E.canon_of_lex, E.v, nullptr, E.csw, E.blk, u.idx);
+  combine_body(E.part, E.nk2 ? E.t2_rows_of : E.rows_of, E.nk2 ? E.t2_ident : E.k_of_slot, E.M, E.N,
+               E.canon_of_lex, E.v, nullptr, E.csw, E.blk, u.idx);
 }
 
 // one block per listed configuration: Phi and S_max of the iterate
@@ -766,6 +783,11 @@ hipError_t launch_nk(const LaunchCfg& c, const Span* segs, int64_t nseg, const N
     case 3: return launch_nk_d<3>(c, segs, nseg, units, nunits, tab, part, so, st, active);
     default: return launch_nk_d<4>(c, segs, nseg, units, nunits, tab, part, so, st, active);
   }
+}
+
+hipError_t launch_batch_nk2(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_nk2, dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate);
+  return hipGetLastError();
 }
 
 hipError_t launch_nk2(const int32_t* tiles, int64_t ntiles, const int32_t* lexinfo, int R, const double* tab,

@@ -118,3 +118,37 @@ def test_batch_precision_option_errors(ctx):
         with pytest.raises(ss.SSError) as e:
             ctx.minimize_batch([w], [dev(pos)], opts=bad)
         assert e.value.code == ss.SS_EINVAL
+
+
+def test_tiled_pass_in_batch(ctx):
+    """A d = 2 configuration with R >= 48 (N = 5000, chi = 0.45: R2 = 2864, R = 53)
+    takes the tiled n~ pass in its double-double evaluations and the piece walk in
+    FP64: first iterates against the oracle, alone vs mix bitwise, and a staged
+    batch that switches passes on its way to the floor."""
+    big = (2, 5000, 0.45, 0, 1.0, 71)
+    items = [setup(ctx, s) for s in (big, SPECS[1], SPECS[0])]
+    w, n, v, pos = items[0]
+    assert int(np.sqrt(w.R2)) >= 48
+    xs = [dev(it[3]) for it in items]
+    res = ctx.minimize_batch([it[0] for it in items], xs, [it[2] for it in items], opts=dict(max_iter=3, s_floor=0.0))
+    xo, ro, _ = O.minimize(n.cpu().numpy(), None, pos, max_iter=3, s_floor=0.0)
+    assert res[0]["iters"] == ro["iters"] == 3 and res[0]["evals"] == ro["evals"]
+    assert abs((res[0]["phi"][0] - ro["phi"][0]) + (res[0]["phi"][1] - ro["phi"][1])) <= 1e-26 * ro["phi"][0]
+    xg = xs[0].cpu().numpy()
+    assert np.abs((xg[0] - xo[0]) + (xg[1] - xo[1])).max() <= 1e-26
+    # alone vs mix, 30 iterations
+    opts = dict(max_iter=30, s_floor=0.0)
+    xa = dev(pos)
+    ra = ctx.minimize_batch([w], [xa], opts=opts)[0]
+    xs = [dev(it[3]) for it in items]
+    rm = ctx.minimize_batch([it[0] for it in items], xs, [it[2] for it in items], opts=opts)[0]
+    assert np.array_equal(xs[0].cpu().numpy(), xa.cpu().numpy()) and rm["phi"] == ra["phi"]
+    # staged to the floor
+    xs = [dev(it[3]) for it in items]
+    res = ctx.minimize_batch([it[0] for it in items], xs, [it[2] for it in items],
+                             opts=dict(s_floor=FLOOR, precision="staged"))
+    for (wi, ni, vi, pi), x, r in zip(items, xs, res):
+        assert r["status"] == "converged" and 0 < r["iters_fp64"] < r["iters"], r
+        assert oracle_smax(wi, ni, x) <= FLOOR * (1 + 1e-6)
+    print(f"d=2 N=5000 staged in a batch: iters={res[0]['iters']} (fp64 {res[0]['iters_fp64']}) "
+          f"t={res[0]['seconds']:.2f}s")
