@@ -126,8 +126,11 @@ int ss_workspace_size(ss_ctx* ctx, const ss_problem* prob, int op, size_t* bytes
  *   nk_dev       <- n~ as double[4][M] in canonical order (or NULL)
  * where c_jn, s_jn = cos, sin of k_n.r_j.  n_dev is the canonical list from
  * ss_wavevectors for (d, R2); v_dev is double[2][M] (see vkind).  ws is device
- * scratch of at least ss_workspace_size(op = 0) bytes.  Async; SS_EINVAL on
- * bad sizes, NULL required pointers or a short workspace. */
+ * scratch of at least ss_workspace_size(op = 0) bytes (dominated by the phase
+ * table, 32 d (R + 1) N bytes with R = floor(sqrt(R2))).  Async; SS_EINVAL on
+ * bad sizes, NULL required pointers, a short workspace, or a cutoff whose
+ * per-particle table 32 d (R + 1) bytes exceeds 64 KB (d = 2: R > 1023;
+ * d = 3: R > 681). */
 int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
                    const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
                    void* ws, size_t ws_bytes, void* stream);

@@ -17,6 +17,8 @@
 //                  and walks them with one complex dd product per pair,
 //                  looping over a particle chunk whose tables are staged in
 //                  LDS;
+//   * k_nk2        (d = 2, large cutoffs) computes a 16 x 16 tile of
+//                  wavevectors as products of two staged 16-row table slices;
 //   * k_nk_combine sums the chunk partials in a fixed order with the accurate
 //                  dd addition and forms v C, v S, Phi and S_max per block;
 //   * k_grad       is the transposed gradient pass: each lane owns one particle
