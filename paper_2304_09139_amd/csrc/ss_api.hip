@@ -45,6 +45,9 @@ int nk2_blocks_per_cu();
 hipError_t launch_nk2(const int32_t* tiles, int64_t ntiles, const int32_t* lexinfo, int R, const double* tab,
                       int64_t N, int R1, int64_t chunk, int nrows, double* part, int64_t M, hipStream_t st,
                       const int* active);
+hipError_t launch_nk2_64(const int32_t* tiles, int64_t ntiles, const int32_t* lexinfo, int R, const double* tab,
+                         int64_t N, int R1, int64_t chunk, int nrows, double* part, int64_t M, hipStream_t st,
+                         const int* active);
 }  // namespace ss
 
 using namespace ss;
@@ -578,15 +581,20 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
   Plan::NkSched* sc = &pl->nk_sched.at(p->N);
   // d = 2 at large cutoffs: the tiled pass writes its partials by walk position
   const auto t2 = pl->nk2_sched.find(p->N);
-  const bool tiled = !fp64 && pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, p->N, false) && t2 != pl->nk2_sched.end() &&
+  const bool tiled = pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, p->N, false) && t2 != pl->nk2_sched.end() &&
                      t2->second.nrows <= c.P;
   if (tiled) {
     const Plan::Nk2Sched& s2 = t2->second;
     SS_HIP(ctx, timed(ctx, 0, st, pairs, [&] {
-             return launch_nk2(pl->t2_tiles, pl->t2_ntiles, pl->t2_lexinfo, pl->R, tab, p->N, c.R1, s2.chunk, s2.nrows,
-                               part, p->M, st, active);
+             return fp64 ? launch_nk2_64(pl->t2_tiles, pl->t2_ntiles, pl->t2_lexinfo, pl->R, tab, p->N, c.R1, s2.chunk,
+                                         s2.nrows, part, p->M, st, active)
+                         : launch_nk2(pl->t2_tiles, pl->t2_ntiles, pl->t2_lexinfo, pl->R, tab, p->N, c.R1, s2.chunk,
+                                      s2.nrows, part, p->M, st, active);
            }));
-    SS_HIP(ctx, launch_nk_combine(c, part, s2.rows_of, pl->t2_ident, pl->canon_of_lex, v, nk, csw, blk, st, active));
+    if (fp64)
+      SS_HIP(ctx, launch_nk_combine64(c, part, s2.rows_of, pl->t2_ident, pl->canon_of_lex, v, nk, csw, blk, st, active));
+    else
+      SS_HIP(ctx, launch_nk_combine(c, part, s2.rows_of, pl->t2_ident, pl->canon_of_lex, v, nk, csw, blk, st, active));
   } else {
     SS_HIP(ctx, timed(ctx, 0, st, pairs, [&] {
              return fp64 ? launch_nk64(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active)

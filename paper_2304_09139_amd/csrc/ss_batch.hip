@@ -77,7 +77,7 @@ int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot
 }
 
 int64_t max_units(const HostSlot& h) {
-  const int64_t nk = std::max<int64_t>(h.n_nk, h.s2 ? h.n_nk2 : 0);
+  const int64_t nk = h.s2 ? h.n_nk2 : h.n_nk;
   return h.n_table + nk + h.n_comb + h.n_grad + h.n_gcomb + h.n_dots + h.n_vec;
 }
 
@@ -115,9 +115,9 @@ void build_lists(const std::vector<HostSlot>& hs, std::vector<int> active, std::
   for (int ph = 1; ph >= 0; --ph) {
     auto& nkg = ph ? L.nk : L.nk64;
     auto& grg = ph ? L.grad : L.grad64;
-    // n(k) pass grouped by (d, LDS tile); double-double evaluations of d = 2
-    // configurations with a tiled schedule form a group of their own (pt = 0)
-    auto tiled = [&](int s) { return ph == 1 && hs[s].s2 != nullptr; };
+    // n(k) pass grouped by (d, LDS tile); d = 2 configurations with a tiled
+    // schedule form a group of their own (pt = 0)
+    auto tiled = [&](int s) { return hs[s].s2 != nullptr; };
     {
       Lists::Group g{2, 0, 0, (int64_t)U.size(), 0, 0.0};
       for (int s : active)
@@ -297,7 +297,8 @@ hipError_t launch_eval(ss_ctx* ctx, const DevArrays& D, const Lists& L, int whic
   if (e != hipSuccess) return e;
   // configurations in their FP64 stage
   for (const auto& g : L.nk64) {
-    e = launch_batch_nk64(g.d, g.pt, g.R1max, D.es, D.units + g.off, g.n, gate, st);
+    e = g.pt == 0 ? launch_batch_nk2_64(D.es, D.units + g.off, g.n, gate, st)
+                  : launch_batch_nk64(g.d, g.pt, g.R1max, D.es, D.units + g.off, g.n, gate, st);
     if (e != hipSuccess) return e;
   }
   e = launch_batch_combine64(D.es, D.units + L.comb64_off, L.comb64_n, gate, st);

@@ -36,6 +36,7 @@ hipError_t launch_batch_init(const MinSlot* ms, const int32_t* list, int64_t n, 
 hipError_t launch_batch_flags(const MinSlot* ms, const int32_t* list, int64_t n, SlotFlags* out, hipStream_t st);
 hipError_t launch_batch_nk64(int d, int pt, int R1max, const EvalSlot* es, const BUnit* units, int64_t n, int gate,
                              hipStream_t st);
+hipError_t launch_batch_nk2_64(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
 hipError_t launch_batch_combine64(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
 hipError_t launch_batch_grad64(int d, const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st);
 hipError_t launch_batch_gcomb64(const EvalSlot* es, const BUnit* units, int64_t n, int which, int gate,
@@ -50,14 +51,14 @@ struct HostSlot {
   Plan* pl = nullptr;
   LaunchCfg c{};
   Plan::NkSched* sc = nullptr;
-  Plan::Nk2Sched* s2 = nullptr;  // the tiled d = 2 pass of the double-double evaluations, or none
+  Plan::Nk2Sched* s2 = nullptr;  // the tiled d = 2 n(k) pass (both precisions), or none
   int32_t* cb = nullptr;
   int64_t nv = 0;
   int m = 0, G = 0;
   size_t bytes = 0;  // workspace of this configuration (energy + minimiser)
   // unit counts of this configuration's grids
   int64_t n_table = 0, n_nk = 0, n_comb = 0, n_grad = 0, n_gcomb = 0, n_dots = 0, n_vec = 0;
-  int64_t n_nk2 = 0;  // tiles x rows of the tiled pass (dd evaluations when s2 is set)
+  int64_t n_nk2 = 0;  // tiles x rows of the tiled pass (used when s2 is set)
   double work = 0.0;  // M N, for ordering
   int phase = 1;      // evaluation precision now: 0 FP64 (first stage or FP64 only), 1 double-double
 };

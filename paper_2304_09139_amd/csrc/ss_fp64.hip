@@ -299,6 +299,73 @@ __global__ void __launch_bounds__(kThreads) k_grad_combine64(const double* __res
 }
 
 // ---------------------------------------------------------------------------
+// the tiled d = 2 n~(k) pass in FP64: the double-double tiled pass with the high
+// words of the two staged table slices, FP64 complex products and sums;
+// part[(row * 2 + c) * M + walk position]
+// ---------------------------------------------------------------------------
+constexpr int kT2f = 16;
+constexpr int kT2fPitch = kT2f * 2 + 2;  // doubles per staged particle (pad: no bank conflicts)
+
+__device__ __forceinline__ void nk2_64_body(const int32_t* __restrict__ tiles, const int32_t* __restrict__ lexinfo,
+                                            int R, const double* __restrict__ tab, int64_t N, int R1, int64_t chunk,
+                                            int tile, int row, double* __restrict__ part, int64_t M) {
+  __shared__ double s0[kT2f * kT2fPitch], s1[kT2f * kT2fPitch];  // [particle][row][re, im]
+  const int tid = threadIdx.x;
+  const int a0 = tiles[2 * tile], b0 = tiles[2 * tile + 1];
+  const int i0 = tid / kT2f, i1 = tid % kT2f;
+  const int n0 = a0 + i0, n1 = b0 + i1;
+  int64_t pos = -1;
+  if (n0 <= R) {
+    const int off = lexinfo[3 * n0], lo = lexinfo[3 * n0 + 1], hi = lexinfo[3 * n0 + 2];
+    if (n1 >= lo && n1 <= hi) pos = off + (n1 - lo);
+  }
+  const bool mine = pos >= 0;
+  const bool neg = n1 < 0;
+  double cr = 0.0, ci = 0.0;
+  const int64_t j0 = (int64_t)row * chunk;
+  const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
+  for (int64_t tj = j0; tj < j1; tj += kT2f) {
+    const int np = (int)((j1 - tj) < kT2f ? (j1 - tj) : kT2f);
+    __syncthreads();
+    // 2 slices x 16 rows x (re.hi, im.hi) x 16 particles, particle fastest
+#pragma unroll
+    for (int q = 0; q < (2 * kT2f * 2 * kT2f) / kThreads; ++q) {
+      const int idx = tid + kThreads * q;
+      const int p = idx % kT2f, c2 = (idx / kT2f) % 2, r = (idx / (2 * kT2f)) % kT2f, ax = idx / (2 * kT2f * kT2f);
+      const int m = ax == 0 ? a0 + r : (b0 + r < 0 ? -(b0 + r) : b0 + r);
+      double val = 0.0;
+      if (p < np && m <= R) val = tab[((int64_t)(ax * R1 + m) * 4 + 2 * c2) * N + tj + p];
+      (ax == 0 ? s0 : s1)[p * kT2fPitch + r * 2 + c2] = val;
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll 4
+      for (int p = 0; p < np; ++p) {
+        const double* e0 = s0 + p * kT2fPitch + i0 * 2;
+        const double* e1 = s1 + p * kT2fPitch + i1 * 2;
+        const c64 w = cmul64(c64{e0[0], e0[1]}, c64{e1[0], neg ? -e1[1] : e1[1]});
+        cr += w.re;
+        ci += w.im;
+      }
+    }
+  }
+  if (mine) {
+    double* out = part + (int64_t)row * 2 * M;
+    out[pos] = cr;
+    out[M + pos] = ci;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_nk2_64(const int32_t* __restrict__ tiles,
+                                                     const int32_t* __restrict__ lexinfo, int R,
+                                                     const double* __restrict__ tab, int64_t N, int R1,
+                                                     int64_t chunk, int nrows, double* __restrict__ part, int64_t M,
+                                                     const int* __restrict__ active) {
+  if (active && *active == 0) return;
+  nk2_64_body(tiles, lexinfo, R, tab, N, R1, chunk, (int)(blockIdx.x / nrows), (int)(blockIdx.x % nrows), part, M);
+}
+
+// ---------------------------------------------------------------------------
 // batched FP64 launches (the FP64 stage of staged quenches in a batch): the
 // same bodies over the blocks of many configurations, as in the double-double
 // batched kernels
@@ -313,12 +380,22 @@ __global__ void __launch_bounds__(kThreads) kb_nk64(const EvalSlot* __restrict__
   nk64_body<D, PT>(E.segs, E.nsegs, E.units[u.idx], E.tab, E.N, E.R1, E.part, E.M, E.so, lds);
 }
 
+__global__ void __launch_bounds__(kThreads) kb_nk2_64(const EvalSlot* __restrict__ es,
+                                                      const BUnit* __restrict__ units, int gate) {
+  const BUnit u = units[blockIdx.x];
+  const EvalSlot& E = es[u.slot];
+  if (gate && *E.running == 0) return;
+  nk2_64_body(E.t2_tiles, E.t2_lexinfo, E.R, E.tab, E.N, E.R1, E.t2_chunk, u.idx / E.t2_nrows, u.idx % E.t2_nrows,
+              E.part, E.M);
+}
+
 __global__ void __launch_bounds__(kThreads) kb_combine64(const EvalSlot* __restrict__ es,
                                                          const BUnit* __restrict__ units, int gate) {
   const BUnit u = units[blockIdx.x];
   const EvalSlot& E = es[u.slot];
   if (gate && *E.running == 0) return;
-  combine64_body(E.part, E.rows_of, E.k_of_slot, E.M, E.N, E.canon_of_lex, E.v, nullptr, E.csw, E.blk, u.idx);
+  combine64_body(E.part, E.nk2 ? E.t2_rows_of : E.rows_of, E.nk2 ? E.t2_ident : E.k_of_slot, E.M, E.N,
+                 E.canon_of_lex, E.v, nullptr, E.csw, E.blk, u.idx);
 }
 
 template <int D>
@@ -420,6 +497,20 @@ hipError_t launch_batch_nk64(int d, int pt, int R1max, const EvalSlot* es, const
     default: SS_NK64(4, 1); break;
   }
 #undef SS_NK64
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_nk2_64(const EvalSlot* es, const BUnit* units, int64_t n, int gate, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(kb_nk2_64, dim3((unsigned)n), dim3(kThreads), 0, st, es, units, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_nk2_64(const int32_t* tiles, int64_t ntiles, const int32_t* lexinfo, int R, const double* tab,
+                         int64_t N, int R1, int64_t chunk, int nrows, double* part, int64_t M, hipStream_t st,
+                         const int* active) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nk2_64, dim3((unsigned)(ntiles * nrows)), dim3(kThreads), 0, st, tiles, lexinfo, R, tab, N,
+                     R1, chunk, nrows, part, M, active);
   return hipGetLastError();
 }
 

@@ -88,8 +88,8 @@ struct EvalSlot {
   double* phi;             // Phi and S_max of the iterate (the starting evaluation)
   double* smax;
   const int32_t* running;  // the minimiser's running word
-  // the tiled d = 2 n(k) pass of the double-double evaluations (nk2 != 0); the
-  // FP64 evaluations keep the piece walk above
+  // the tiled d = 2 n(k) pass (nk2 != 0), in both precisions, instead of the
+  // piece walk above
   int32_t nk2, R, t2_nrows;
   int64_t t2_chunk;
   const int32_t* t2_tiles;

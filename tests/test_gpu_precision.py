@@ -51,6 +51,7 @@ CASES = [
     ("d4_N77_R2_5", 4, 77, 5, 0, 1.0, 4),
     ("d3_N257_L2.5", 3, 257, 30, 0, 2.5, 5),
     ("d3_N2500_chi0.45", 3, 2500, None, 0, 1.0, 8),
+    ("d2_N300_R2_5000_tiled", 2, 300, 5000, 0, 1.0, 9),
 ]
 
 
