@@ -112,7 +112,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def mp_error_report(ctx, w, n, v, pos, count=6, seed=7):
+def mp_error_report(ctx, w, n, v, pos, count=32, seed=7, label=""):
     """n~(k) at sampled wavevectors (the smallest |k|, the outermost shell and
     random ones) from the double-double and the FP64 passes, against a 256-bit
     mpmath evaluation of the same sums (phases n.u taken exactly from the dd
@@ -130,7 +130,9 @@ def mp_error_report(ctx, w, n, v, pos, count=6, seed=7):
     ks = sorted(set([0, w.M - 1] + [int(k) for k in rng.choice(w.M, count - 2, replace=False)]))
     u = [[mp.mpf(float(ph[0, a, j])) + mp.mpf(float(ph[1, a, j])) for j in range(w.N)] for a in range(w.d)]
     rows = []
-    for k in ks:
+    for q, k in enumerate(ks):
+        if q % 4 == 0:
+            print(f"[bench] 256-bit n~ {label}: wavevector {q + 1} of {len(ks)}", file=sys.stderr, flush=True)
         C = mp.mpf(0)
         S = mp.mpf(0)
         for j in range(w.N):
@@ -190,6 +192,7 @@ def main():
                     help="skip the staged-precision quenches of the same starts (single and batched workloads)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched workloads: skip timing the same configurations one at a time")
+    ap.add_argument("--mp-k", type=int, default=32, help="sampled wavevectors of the 256-bit report")
     ap.add_argument("--mp-report", action="store_true",
                     help="report the 256-bit error of n~ at sampled k of the final configuration")
     ap.add_argument("--method", default="lbfgs", choices=("lbfgs", "fire"),
@@ -395,7 +398,18 @@ def main():
     }
     if args.precision == "staged" or args.mp_report:
         # 256-bit error of the reported n~ / S(k) at the final positions of the last quench
-        out["error_vs_mp256_final"] = mp_error_report(ctx, w, n, v, starts[args.warmup + args.steps - 1])
+        rep = {"final": mp_error_report(ctx, w, n, v, starts[args.warmup + args.steps - 1], count=args.mp_k,
+                                        label="at the end")}
+        if args.precision == "staged":
+            # the switch point: the FP64 stage alone from the same start (the same
+            # kernels and stage parameters, so the same iterates)
+            xs = torch.from_numpy(inputs.config_positions(wl["cfg_id"], d, N, args.warmup + args.steps - 1)).cuda()
+            r64 = ctx.minimize(w, n, v, xs, **dict(mopts, precision="fp64",
+                                                   s_floor=max(FLOOR, ss.DEFAULT_MIN_OPTS["fp64_floor"]),
+                                                   max_ls_fail=1))
+            rep["switch"] = dict(mp_error_report(ctx, w, n, v, xs, count=args.mp_k, label="at the switch"),
+                                 fp64_iters=r64["iters"], smax_fp64=r64["smax"][0])
+        out["error_vs_mp256"] = rep
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, N, chi, wl["cfg_id"])
     print(json.dumps(out), flush=True)
