@@ -537,7 +537,8 @@ def bench_batch(args, wl):
         ctx.workspace(max(works, key=lambda w: ctx.workspace_size(w, 1)), 1)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        seq_res = [ctx.minimize(w, n, None, x, **opts) for w, n, x in zip(works, wsn, seq)]
+        # the plain path: double-double, one configuration per ss_minimize call
+        seq_res = [ctx.minimize(w, n, None, x, **dict(opts, precision="dd")) for w, n, x in zip(works, wsn, seq)]
         torch.cuda.synchronize()
         seq_elapsed = time.perf_counter() - t1
         seq_conv = sum(1 for r in seq_res if r["status"] == "converged")
@@ -563,10 +564,13 @@ def bench_batch(args, wl):
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{len(results)}",
         "fp64_pairs_per_s": pairs64 / elapsed,
-        "staged_precision": staged,
+        "staged_precision": None if staged is None else dict(
+            staged, speedup_vs_one_at_a_time_dd=None if args.no_sequential else
+            staged["configs_per_s"] / (seq_conv / seq_elapsed)),
         "smax_worst": max(r["smax"][0] for r in results),
         "one_at_a_time": None if args.no_sequential else {
-            "configs_per_s": seq_conv / seq_elapsed, "seconds": seq_elapsed, "converged": f"{seq_conv}/{count}"},
+            "configs_per_s": seq_conv / seq_elapsed, "seconds": seq_elapsed, "converged": f"{seq_conv}/{count}",
+            "precision": "dd"},
         "speedup_vs_one_at_a_time": None if args.no_sequential else (converged / elapsed) / (seq_conv / seq_elapsed),
         "tiles": "tuned table" if ctx_tuned else "built-in",
         "latency_s": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(0.99 * len(lat)))],
@@ -648,7 +652,7 @@ def bench_serve(args, wl):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for w, n, x in zip(works, ns, xs):
-            r = ctx.minimize(w, n, None, x, s_floor=FLOOR, precision=args.precision)
+            r = ctx.minimize(w, n, None, x, s_floor=FLOOR)  # the plain path: double-double
             seq_conv += r["status"] == "converged"
         torch.cuda.synchronize()
         seq_s = time.perf_counter() - t1
@@ -677,7 +681,7 @@ def bench_serve(args, wl):
         "converged": f"{conv}/{count}",
         "capacity_configs_per_s": cap,
         "one_at_a_time": None if args.no_sequential else {
-            "configs_per_s": seq_conv / seq_s, "seconds": seq_s, "converged": f"{seq_conv}/{count}"},
+            "configs_per_s": seq_conv / seq_s, "seconds": seq_s, "converged": f"{seq_conv}/{count}", "precision": "dd"},
         "capacity_vs_one_at_a_time": None if args.no_sequential else cap / (seq_conv / seq_s),
         "arrival_rate_per_s": lam,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
