@@ -129,8 +129,9 @@ int ss_workspace_size(ss_ctx* ctx, const ss_problem* prob, int op, size_t* bytes
  * scratch of at least ss_workspace_size(op = 0) bytes (dominated by the phase
  * table, 32 d (R + 1) N bytes with R = floor(sqrt(R2))).  Async; SS_EINVAL on
  * bad sizes, NULL required pointers, a short workspace, or a cutoff whose
- * per-particle table 32 d (R + 1) bytes exceeds 64 KB (d = 2: R > 1023;
- * d = 3: R > 681). */
+ * per-particle table 32 d (R + 1) bytes exceeds 64 KB (d = 1: R > 2047;
+ * d = 3: R > 681; d = 4: R > 511; d = 2 has no such limit: from R = 48 on it
+ * stages 32 table rows per particle whatever R is). */
 int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
                    const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
                    void* ws, size_t ws_bytes, void* stream);

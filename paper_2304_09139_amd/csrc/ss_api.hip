@@ -425,9 +425,13 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const Til
   c->R1 = pl->R + 1;
   const size_t per_particle = (size_t)p->d * c->R1 * 4 * sizeof(double);
   const size_t lds_budget = 64 * 1024;
+  // d = 2 from R = kNk2MinR on: every n(k) pass (single, batched, FP64) is the
+  // tiled one, which stages 32 table rows whatever R is; the piece walk, which
+  // stages whole particle tables in LDS, is not used
+  const bool tiles_only = p->d == 2 && pl->R >= kNk2MinR && pl->t2_ntiles > 0;
   if (16 * per_particle <= lds_budget) c->pt = 16;
   else if (4 * per_particle <= lds_budget) c->pt = 4;
-  else if (per_particle <= lds_budget) c->pt = 1;
+  else if (per_particle <= lds_budget || tiles_only) c->pt = 1;
   else return set_err(ctx, SS_EINVAL, "cutoff radius too large for the LDS particle tables");
   c->segblocks = (pl->nsegs + kNkPieces - 1) / kNkPieces;
   Plan::NkSched* sc = nullptr;
@@ -436,7 +440,7 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const Til
                   : nk_schedule(ctx, pl, c->N, c->pt, &sc);
     if (rc) return rc;
   }
-  c->P = sc->rows;
+  c->P = tiles_only ? 1 : sc->rows;
   if (pl->t2_ntiles > 0 && use_nk2(p->d, pl->R, c->N, tile != nullptr)) {  // partial rows of the tiled d = 2 pass
     Plan::Nk2Sched* s2 = nullptr;
     int rc = tile ? nk2_schedule_fixed(ctx, pl, c->N, tile->nk_chunk, &s2) : nk2_schedule(ctx, pl, c->N, &s2);
@@ -596,6 +600,7 @@ int energy_grad_impl(ss_ctx* ctx, const ss_problem* p, Plan* pl, const LaunchCfg
     else
       SS_HIP(ctx, launch_nk_combine(c, part, s2.rows_of, pl->t2_ident, pl->canon_of_lex, v, nk, csw, blk, st, active));
   } else {
+    if (sc->rows > c.P) return set_err(ctx, SS_EHIP, "n(k) partial rows exceed the workspace layout");
     SS_HIP(ctx, timed(ctx, 0, st, pairs, [&] {
              return fp64 ? launch_nk64(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active)
                          : launch_nk(c, pl->segs, pl->nsegs, sc->units, sc->nunits, tab, part, pl->slot_off, st, active);

@@ -82,6 +82,8 @@ CASES = [
     ("d2_N300_R2_5000_lds4", 2, 300, 5000, 0, 1.0, 9),
     ("d3_N100_R2_1900_lds4_weighted", 3, 100, 1900, 1, 1.0, 10),
     ("d2_N200_R2_70000_lds1", 2, 200, 70000, 0, 1.0, 12),
+    # d = 2 beyond the 64 KB particle table (R = 1030): only the tiled pass runs
+    ("d2_N40_R2_1060900_tiles_only", 2, 40, 1030 * 1030, 0, 1.0, 13),
 ]
 
 
@@ -196,12 +198,12 @@ def test_invalid_arguments(ctx):
                                  None, None, ss._ptr(small), 16, None)
     assert rc == ss.SS_EINVAL
     # a cutoff whose particle table (d (R + 1) dd complex entries) exceeds the
-    # 64 KB LDS tile is rejected: d = 2, R = 1030
-    R2b = 1030 * 1030
-    wb = ss.Workload(2, 10, R2b, ss.count(2, R2b))
-    nb = ctx.wavevectors(2, R2b)
+    # 64 KB LDS tile of the piece walk is rejected: d = 1, R = 2048
+    R2b = 2048 * 2048
+    wb = ss.Workload(1, 10, R2b, ss.count(1, R2b))
+    nb = ctx.wavevectors(1, R2b)
     with pytest.raises(ss.SSError) as e:
-        ctx.energy_grad(wb, nb, None, dev(inputs.uniform_positions(2, 10, 3)))
+        ctx.energy_grad(wb, nb, None, dev(inputs.uniform_positions(1, 10, 3)))
     assert e.value.code == ss.SS_EINVAL
 
 
