@@ -305,16 +305,28 @@ int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs, const dou
  * to ss_minimize_batch's result for it.  ss_submit and ss_poll may be called
  * from any thread.  Do not change the tile table while a server runs. */
 
-/* One quench request.  The starting positions are copied by ss_submit. */
+/* One quench request.  The starting positions are copied by ss_submit, or,
+ * with pos_host NULL, drawn by ss_uniform_positions from seed (a Poisson start,
+ * the paper's initial condition). */
 typedef struct {
   int32_t d;               /* 1..4                                                     */
   int64_t N;               /* particles                                                */
   int64_t R2;              /* cutoff |n|^2 <= R2 (ss_cutoff gives it from chi)          */
   double L;                /* box side                                                 */
   int32_t vkind;           /* 0: v = 1; 1: v = (1 - |k|/K)^2, computed by the library   */
-  const double* pos_host;  /* double[2][d][N] fractional starting positions (host)      */
+  const double* pos_host;  /* double[2][d][N] fractional starting positions (host), or NULL */
+  uint64_t seed;           /* the start's seed when pos_host is NULL                   */
   ss_min_opts opts;        /* minimiser options (L-BFGS: method 0; any precision)      */
 } ss_request;
+
+/* Independent uniform fractional positions in [0, 1)^d (the paper's Poisson
+ * initial condition, "Simulations") as double[2][d][N] (host): coordinate
+ * (a, j) is the exact 106-bit dyadic u = A 2^-53 + B 2^-106, A and B the top 53
+ * bits of outputs 2 (a N + j) + 1 and 2 (a N + j) + 2 of the SplitMix64
+ * sequence (Steele, Lea and Flood, OOPSLA 2014) started at seed, stored as
+ * hi = u rounded to nearest and lo = u - hi (exact).  Host only, pure.
+ * SS_EINVAL for d outside 1..4, N < 1 or a NULL output. */
+int ss_uniform_positions(int d, int64_t N, uint64_t seed, double* pos_host_out);
 
 /* Start the server.  arena_dev: caller-owned device memory that holds every
  * running configuration's workspace (ss_batch_workspace_size of a single
@@ -327,7 +339,7 @@ int ss_server_start(ss_ctx* ctx, void* arena_dev, size_t arena_bytes, int max_sl
 
 /* Queue one request; *ticket identifies it for ss_poll.  Non-blocking apart
  * from building the wavevector plan of a new (d, R2) on first use.  SS_EINVAL
- * for an invalid request (shape, vkind, options, NULL or non-finite positions),
+ * for an invalid request (shape, vkind, options, non-finite positions),
  * SS_ESTATE without a running server or while it stops, or the server's error
  * after a failure. */
 int ss_submit(ss_ctx* ctx, const ss_request* req, uint64_t* ticket);

@@ -703,6 +703,27 @@ const char* ss_strerror(int code) {
 
 const char* ss_last_error(ss_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
 
+int ss_uniform_positions(int d, int64_t N, uint64_t seed, double* out) {
+  if (d < 1 || d > 4 || N < 1 || !out) return SS_EINVAL;
+  // SplitMix64 (Steele, Lea, Flood 2014): output i (from 1) of the sequence
+  // started at seed is the finaliser of seed + i * golden gamma
+  auto output = [seed](uint64_t i) {
+    uint64_t z = seed + i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  const int64_t DN = (int64_t)d * N;
+  for (int64_t e = 0; e < DN; ++e) {  // e = a N + j
+    const double ta = std::ldexp((double)(output((uint64_t)(2 * e + 1)) >> 11), -53);   // exact
+    const double tb = std::ldexp((double)(output((uint64_t)(2 * e + 2)) >> 11), -106);  // exact
+    const double hi = ta + tb;  // u rounded to nearest
+    out[e] = hi;
+    out[DN + e] = (ta - hi) + tb;  // u - hi, exact
+  }
+  return SS_OK;
+}
+
 int ss_count(int d, int64_t R2, int64_t* M) {
   if (!M || d < 1 || d > 4 || R2 < 1 || isqrt64(R2) > 32767) return SS_EINVAL;
   *M = count_half(d, R2);

@@ -471,8 +471,8 @@ class Worker {
 };
 
 int check_request(ss_ctx* ctx, const ss_request* q, ss_problem* p) {
-  if (!q || !q->pos_host) {
-    ctx->last_error = "NULL request or positions";
+  if (!q) {
+    ctx->last_error = "NULL request";
     return SS_EINVAL;
   }
   int64_t M = 0;
@@ -564,7 +564,13 @@ extern "C" int ss_submit(ss_ctx* ctx, const ss_request* req, uint64_t* ticket) {
   r->opts = req->opts;
   rc = eng::setup_slot(ctx, &p, &req->opts, &r->h);
   if (rc) return rc;
-  r->pos.assign(req->pos_host, req->pos_host + (size_t)2 * p.d * p.N);
+  if (req->pos_host) {
+    r->pos.assign(req->pos_host, req->pos_host + (size_t)2 * p.d * p.N);
+  } else {
+    r->pos.resize((size_t)2 * p.d * p.N);
+    rc = ss_uniform_positions(p.d, p.N, req->seed, r->pos.data());
+    if (rc) return rc;
+  }
   for (double x : r->pos)
     if (!isfinite(x)) {
       ctx->last_error = "positions are not finite";

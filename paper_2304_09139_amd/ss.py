@@ -53,7 +53,8 @@ class Tile(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int64), ("R2", ctypes.c_int64), ("L", ctypes.c_double),
-                ("vkind", ctypes.c_int32), ("pos_host", ctypes.c_void_p), ("opts", MinOpts)]
+                ("vkind", ctypes.c_int32), ("pos_host", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+                ("opts", MinOpts)]
 
 
 _V = ctypes.c_void_p
@@ -67,6 +68,7 @@ SIGNATURES = {
     "ss_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ss_last_error": (ctypes.c_char_p, [_V]),
     "ss_count": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _I64P]),
+    "ss_uniform_positions": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, _V]),
     "ss_cutoff": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_double, _I64P, _I64P]),
     "ss_wavevectors": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int64, _V, ctypes.c_int64, _I64P, _V]),
     "ss_weights": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V]),
@@ -131,6 +133,16 @@ def count(d: int, R2: int) -> int:
     M = ctypes.c_int64()
     _check(lib().ss_count(d, R2, ctypes.byref(M)), what="ss_count")
     return M.value
+
+
+def uniform_positions(d: int, N: int, seed: int):
+    """The library's seeded uniform start (ss_uniform_positions) as float64[2, d, N]."""
+    import numpy as np
+
+    out = np.empty((2, d, N), dtype=np.float64)
+    _check(lib().ss_uniform_positions(d, N, seed & 0xFFFFFFFFFFFFFFFF, out.ctypes.data_as(ctypes.c_void_p)),
+           what="ss_uniform_positions")
+    return out
 
 
 def cutoff(d: int, N: int, chi: float) -> tuple[int, int]:
@@ -364,14 +376,19 @@ class Context:
         torch.cuda.synchronize()
         self._chk(lib().ss_server_start(self._h, _ptr(self._arena), arena_bytes, max_slots), "ss_server_start")
 
-    def submit(self, w: Workload, pos, **opts) -> int:
-        """Queue a quench of host positions pos (float64 [2, d, N]); returns its ticket."""
+    def submit(self, w: Workload, pos=None, seed: int = 0, **opts) -> int:
+        """Queue a quench of host positions pos (float64 [2, d, N]), or with pos
+        None of the library's uniform start drawn from seed; returns its ticket."""
         import numpy as np
 
-        p = np.ascontiguousarray(pos, dtype=np.float64)
-        if p.shape != (2, w.d, w.N):
-            raise ValueError("positions must be [2, d, N]")
-        req = Request(w.d, w.N, w.R2, w.L, w.vkind, p.ctypes.data, _min_opts(opts))
+        if pos is None:
+            p = None
+            req = Request(w.d, w.N, w.R2, w.L, w.vkind, None, seed & 0xFFFFFFFFFFFFFFFF, _min_opts(opts))
+        else:
+            p = np.ascontiguousarray(pos, dtype=np.float64)
+            if p.shape != (2, w.d, w.N):
+                raise ValueError("positions must be [2, d, N]")
+            req = Request(w.d, w.N, w.R2, w.L, w.vkind, p.ctypes.data, 0, _min_opts(opts))
         t = ctypes.c_uint64()
         self._chk(lib().ss_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "ss_submit")
         self._served = getattr(self, "_served", {})

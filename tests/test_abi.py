@@ -61,3 +61,20 @@ def test_host_entry_points_reject_invalid():
         assert e.value.code == ss.SS_EINVAL
     with pytest.raises(ss.SSError):
         ss.count(2, 0)
+
+
+def test_uniform_positions_match_shared_generator():
+    """The library's seeded start (host only) is bitwise the shared generator's
+    (two independent implementations of SplitMix64 and the dyadic mapping)."""
+    from paper_2304_09139_amd import inputs
+
+    for d, N, seed in [(1, 1, 0), (2, 128, inputs.stream_seed(1, 0)), (3, 1000, 2 ** 64 - 1), (4, 77, 12345),
+                       (3, 5, 0x9E3779B97F4A7C15)]:
+        a = ss.uniform_positions(d, N, seed)
+        assert np.array_equal(a, inputs.uniform_positions(d, N, seed)), (d, N, seed)
+        u = a[0] + a[1]
+        assert np.all((u >= 0.0) & (u < 1.0))
+        assert np.all(np.abs(a[1]) <= np.spacing(np.abs(a[0])) / 2)   # normalised pairs
+    for args in [(0, 10, 1), (5, 10, 1), (2, 0, 1)]:
+        with pytest.raises(ss.SSError):
+            ss.uniform_positions(*args)

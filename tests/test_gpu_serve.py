@@ -129,6 +129,23 @@ def test_served_staged_equals_batch(ctx):
         ctx.server_stop()
 
 
+def test_seeded_request_equals_given_start(ctx):
+    """A request without positions starts from the library's uniform start of its
+    seed: the same bits as the request that passes that start explicitly."""
+    w, _ = make(SPECS[0])
+    seed = inputs.stream_seed(47, 3)
+    pos = inputs.uniform_positions(w.d, w.N, seed)
+    ctx.server_start(1 << 28, max_slots=4)
+    try:
+        t0 = ctx.submit(w, None, seed=seed, s_floor=FLOOR)
+        t1 = ctx.submit(w, pos, s_floor=FLOOR)
+        (r0, x0), (r1, x1) = wait(ctx, t0), wait(ctx, t1)
+        assert np.array_equal(x0, x1) and r0["phi"] == r1["phi"] and r0["iters"] == r1["iters"]
+        assert r0["status"] == "converged"
+    finally:
+        ctx.server_stop()
+
+
 def test_small_arena_admission(ctx):
     """An arena that holds about one configuration at a time still serves all
     requests, one after another; a request larger than the arena fails alone."""
