@@ -605,7 +605,9 @@ def bench_serve(args, wl):
     n_min, n_max = wl.get("n_min", 500), wl.get("n_max", 5000)
     stream = inputs.serve_stream(count, seed=wl["stream_seed"], n_min=n_min, n_max=n_max)
     works = [ss.Workload.from_chi(d, N, chi) for d, N, chi, _ in stream]
-    starts = [inputs.config_positions(wl["cfg_id"], w.d, w.N, i) for i, w in enumerate(works)]
+    # a request is (d, N, chi, seed): the server draws the uniform start of the
+    # seed itself (the same positions as inputs.config_positions)
+    seeds = [inputs.stream_seed(wl["cfg_id"], i) for i in range(count)]
     ctx = ss.Context(0, tiles="tuned")
     arena = wl.get("arena_gb", 8) << 30
     ctx.server_start(arena, max_slots=512)
@@ -619,7 +621,7 @@ def bench_serve(args, wl):
         while len(done) < count:
             now = time.perf_counter() - t0
             while i < count and times[i] <= now:
-                tickets.append(ctx.submit(works[i], starts[i], s_floor=FLOOR, precision=args.precision))
+                tickets.append(ctx.submit(works[i], None, seed=seeds[i], s_floor=FLOOR, precision=args.precision))
                 i += 1
             for k, t in enumerate(tickets):
                 if k not in done:
@@ -633,7 +635,7 @@ def bench_serve(args, wl):
         return time.perf_counter() - t0, [done[k] for k in range(count)]
 
     # warm-up: a few short requests (server buffers, first launches)
-    warm = [ctx.submit(works[i], starts[i], max_iter=2) for i in range(min(count, 8))]
+    warm = [ctx.submit(works[i], None, seed=seeds[i], max_iter=2) for i in range(min(count, 8))]
     for t in warm:
         while ctx.poll(t) is None:
             time.sleep(0.001)
@@ -647,7 +649,7 @@ def bench_serve(args, wl):
         # the same requests quenched one at a time with ss_minimize (same floor)
         import torch
 
-        xs = [torch.from_numpy(p).cuda() for p in starts]
+        xs = [torch.from_numpy(inputs.uniform_positions(w.d, w.N, sd)).cuda() for w, sd in zip(works, seeds)]
         ns = [ctx.wavevectors(w.d, w.R2) for w in works]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
