@@ -34,7 +34,8 @@ def dev(a):
 # (d, N, chi, vkind, L, config id): mixed dimensions, sizes (several n(k) units
 # and gradient chunks, ragged tails), weights and box sides
 MIX = [(2, 128, 0.4, 0, 1.0, 11), (3, 300, 0.3, 1, 1.0, 12), (2, 90, 0.35, 0, 3.0, 13),
-       (3, 700, 0.45, 0, 1.0, 14), (1, 40, 0.4, 0, 1.0, 15), (2, 1500, 0.2, 0, 2.0, 16)]
+       (3, 700, 0.45, 0, 1.0, 14), (1, 40, 0.4, 0, 1.0, 15), (2, 1500, 0.2, 0, 2.0, 16),
+       (4, 60, 0.3, 1, 1.0, 17)]
 
 
 def setup(ctx, spec):
@@ -75,7 +76,7 @@ def test_alone_vs_mix_bitwise(ctx):
         x = dev(pos)
         r = ctx.minimize_batch([w], [x], [v], opts=opts)[0]
         alone.append((x.cpu().numpy(), r))
-    order = [3, 0, 5, 2, 4, 1]
+    order = [3, 6, 0, 5, 2, 4, 1]
     for perm in (list(range(len(items))), order):
         xs = [dev(items[i][3]) for i in perm]
         res = ctx.minimize_batch([items[i][0] for i in perm], xs, [items[i][2] for i in perm], opts=opts)
