@@ -324,20 +324,32 @@ __device__ __forceinline__ void nk2_64_body(const int32_t* __restrict__ tiles, c
   double cr = 0.0, ci = 0.0;
   const int64_t j0 = (int64_t)row * chunk;
   const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
-  for (int64_t tj = j0; tj < j1; tj += kT2f) {
+  // 2 slices x 16 rows x (re.hi, im.hi) x 16 particles, particle fastest; the
+  // next chunk's values are loaded into registers while the current one is used
+  constexpr int kQ = (2 * kT2f * 2 * kT2f) / kThreads;
+  double pre[kQ];
+  auto fetch = [&](int64_t tj) {
     const int np = (int)((j1 - tj) < kT2f ? (j1 - tj) : kT2f);
-    __syncthreads();
-    // 2 slices x 16 rows x (re.hi, im.hi) x 16 particles, particle fastest
 #pragma unroll
-    for (int q = 0; q < (2 * kT2f * 2 * kT2f) / kThreads; ++q) {
+    for (int q = 0; q < kQ; ++q) {
       const int idx = tid + kThreads * q;
       const int p = idx % kT2f, c2 = (idx / kT2f) % 2, r = (idx / (2 * kT2f)) % kT2f, ax = idx / (2 * kT2f * kT2f);
       const int m = ax == 0 ? a0 + r : (b0 + r < 0 ? -(b0 + r) : b0 + r);
-      double val = 0.0;
-      if (p < np && m <= R) val = tab[((int64_t)(ax * R1 + m) * 4 + 2 * c2) * N + tj + p];
-      (ax == 0 ? s0 : s1)[p * kT2fPitch + r * 2 + c2] = val;
+      pre[q] = (p < np && m <= R) ? tab[((int64_t)(ax * R1 + m) * 4 + 2 * c2) * N + tj + p] : 0.0;
+    }
+  };
+  if (j0 < j1) fetch(j0);
+  for (int64_t tj = j0; tj < j1; tj += kT2f) {
+    const int np = (int)((j1 - tj) < kT2f ? (j1 - tj) : kT2f);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int idx = tid + kThreads * q;
+      const int p = idx % kT2f, c2 = (idx / kT2f) % 2, r = (idx / (2 * kT2f)) % kT2f, ax = idx / (2 * kT2f * kT2f);
+      (ax == 0 ? s0 : s1)[p * kT2fPitch + r * 2 + c2] = pre[q];
     }
     __syncthreads();
+    if (tj + kT2f < j1) fetch(tj + kT2f);
     if (mine) {
 #pragma unroll 4
       for (int p = 0; p < np; ++p) {

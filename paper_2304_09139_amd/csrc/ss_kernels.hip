@@ -216,20 +216,32 @@ __device__ __forceinline__ void nk2_body(const int32_t* __restrict__ tiles, cons
   double crh = 0.0, crl = 0.0, cih = 0.0, cil = 0.0;
   const int64_t j0 = (int64_t)row * chunk;
   const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
-  for (int64_t tj = j0; tj < j1; tj += kT2) {
+  // 2 slices x 16 rows x 4 components x 16 particles, particle fastest; the
+  // next chunk's values are loaded into registers while the current one is used
+  constexpr int kQ = (2 * kT2 * 4 * kT2) / kThreads;
+  double pre[kQ];
+  auto fetch = [&](int64_t tj) {
     const int np = (int)((j1 - tj) < kT2 ? (j1 - tj) : kT2);
-    __syncthreads();
-    // 2 slices x 16 rows x 4 components x 16 particles, particle fastest
 #pragma unroll
-    for (int q = 0; q < (2 * kT2 * 4 * kT2) / kThreads; ++q) {
+    for (int q = 0; q < kQ; ++q) {
       const int idx = tid + kThreads * q;
       const int p = idx % kT2, c = (idx / kT2) % 4, r = (idx / (4 * kT2)) % kT2, ax = idx / (4 * kT2 * kT2);
       const int m = ax == 0 ? a0 + r : (b0 + r < 0 ? -(b0 + r) : b0 + r);
-      double val = 0.0;
-      if (p < np && m <= R) val = tab[((int64_t)(ax * R1 + m) * 4 + c) * N + tj + p];
-      (ax == 0 ? s0 : s1)[p * kT2Pitch + r * 4 + c] = val;
+      pre[q] = (p < np && m <= R) ? tab[((int64_t)(ax * R1 + m) * 4 + c) * N + tj + p] : 0.0;
+    }
+  };
+  if (j0 < j1) fetch(j0);
+  for (int64_t tj = j0; tj < j1; tj += kT2) {
+    const int np = (int)((j1 - tj) < kT2 ? (j1 - tj) : kT2);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int idx = tid + kThreads * q;
+      const int p = idx % kT2, c = (idx / kT2) % 4, r = (idx / (4 * kT2)) % kT2, ax = idx / (4 * kT2 * kT2);
+      (ax == 0 ? s0 : s1)[p * kT2Pitch + r * 4 + c] = pre[q];
     }
     __syncthreads();
+    if (tj + kT2 < j1) fetch(tj + kT2);
     if (mine) {
 #pragma unroll 4
       for (int p = 0; p < np; ++p) {
