@@ -82,6 +82,8 @@ CASES = [
     ("d2_N300_R2_5000_lds4", 2, 300, 5000, 0, 1.0, 9),
     ("d3_N100_R2_1900_lds4_weighted", 3, 100, 1900, 1, 1.0, 10),
     ("d2_N200_R2_70000_lds1", 2, 200, 70000, 0, 1.0, 12),
+    # the tiled pass of a small d = 2 system (R = 20, N <= 2500), weighted, L != 1
+    ("d2_N500_R2_400_L3_weighted_tiled", 2, 500, 400, 1, 3.0, 14),
     # d = 2 beyond the 64 KB particle table (R = 1030): only the tiled pass runs
     ("d2_N40_R2_1060900_tiles_only", 2, 40, 1030 * 1030, 0, 1.0, 13),
 ]
