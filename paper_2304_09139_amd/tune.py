@@ -26,6 +26,10 @@ NK_CHUNKS = (32, 64, 128, 256)
 GRAD_KS = (256, 512, 1024, 2048)
 # (d, N range) buckets; M follows from chi in {0.2, 0.35, 0.45}
 BUCKETS = [(2, 500, 1000), (2, 1000, 2000), (2, 2000, 5000), (3, 500, 1000), (3, 1000, 2000), (3, 2000, 5000)]
+# larger systems (served requests up to N = 1e5): fewer configurations per batch
+# and longer particle chunks
+LARGE_BUCKETS = [(2, 5000, 20000), (2, 20000, 100000), (3, 5000, 20000), (3, 20000, 100000)]
+NK_CHUNKS_LARGE = (128, 256, 512, 1024)
 
 
 def load_tiles(path: str = TILES_PATH) -> list[dict]:
@@ -43,12 +47,13 @@ def tune(count: int = 48, iters: int = 12, out: str = TILES_PATH) -> list[dict]:
 
     ctx = ss.Context(0)
     entries = []
-    for d, n_lo, n_hi in BUCKETS:
-        shapes = inputs.batch_shapes(count, seed=100 + d * 10 + n_lo // 500, n_min=n_lo, n_max=n_hi, dims=(d,))
+    plan = [(b, count, NK_CHUNKS) for b in BUCKETS] + [(b, max(4, count // 8), NK_CHUNKS_LARGE) for b in LARGE_BUCKETS]
+    for (d, n_lo, n_hi), cnt, chunks in plan:
+        shapes = inputs.batch_shapes(cnt, seed=100 + d * 10 + n_lo // 500, n_min=n_lo, n_max=n_hi, dims=(d,))
         works = [ss.Workload.from_chi(dd, N, chi) for dd, N, chi in shapes]
         starts = [inputs.config_positions(7, w.d, w.N, i) for i, w in enumerate(works)]
         best = None
-        for nk_chunk in NK_CHUNKS:
+        for nk_chunk in chunks:
             for grad_k in GRAD_KS:
                 ctx.set_tiles([dict(d=0, max_N=1 << 40, max_M=1 << 40, nk_chunk=nk_chunk, grad_k=grad_k)])
                 rate = []
