@@ -111,20 +111,49 @@ def grad_fd(n, v, pos, j, a, L=1.0, h=ctx.mpf(2) ** -100):
 # --- L-BFGS rules, second implementation ------------------------------------
 
 def lbfgs_mp(fg, x0, nmean, max_iter, history=8, c1=1e-4, step_cap=1e-2, max_halvings=40):
-    """Run the minimiser rules for ``max_iter`` iterations at 256 bits.
+    """Run the minimiser rules for ``max_iter`` iterations at 256 bits with no
+    stopping rule other than the count; returns (x, list of f at each iterate)."""
+    x, trace, _, _ = lbfgs_mp_run(fg, x0, nmean, max_iter, history, c1, step_cap, max_halvings)
+    return x, trace
 
-    fg(x) -> (f, g list).  Returns (x, list of f at each iterate).  Rules: the
-    two-loop recursion with H0 = (s.y / y.y) I of the newest pair; a
-    steepest-descent step scaled to move at most step_cap * nmean, and at most
-    to 2 f / g.g (the minimum value is 0), when the history is empty or the
-    direction is not a descent direction; Armijo
-    backtracking by halving from alpha = 1; a pair is kept only when s.y > 0.
+
+def lbfgs_mp_run(fg, x0, nmean, max_iter, history=8, c1=1e-4, step_cap=1e-2, max_halvings=40,
+                 stall_window=None, stall_ratio=0.99, max_ls_fail=None):
+    """The minimiser rules at 256 bits, with the stopping rules.
+
+    fg(x) -> (f, g list).  Rules: the two-loop recursion with H0 = (s.y / y.y) I
+    of the newest pair; a steepest-descent step scaled to move at most
+    step_cap * nmean, and at most to 2 f / g.g (the minimum value is 0), when the
+    history is empty or the direction is not a descent direction; Armijo
+    backtracking by halving from alpha = 1 (max_halvings halvings, then a
+    failure: the history is cleared and x kept); a pair is kept only when
+    s.y > 0.  Stopping rules, tested at the top of every iteration in this
+    order: the iteration cap; with stall_window W, stalled when the smallest f
+    of the last W iterates exceeds stall_ratio times the smallest of the W
+    before them (tested once 2W iterations are done); and, with max_ls_fail,
+    stalled right after that many consecutive failures.
+
+    Returns (x, trace, status, iterations): trace holds f at the top of every
+    iteration reached (a run ending on failures has no entry for its last
+    count), status is "stalled" or "max_iter".
     """
     x = list(x0)
     f, g = fg(x)
     S, Y, R = [], [], []
-    trace = [f]
-    for _ in range(max_iter):
+    trace = []
+    hist = []          # f at every iterate, for the stall window
+    it = 0
+    fails = 0
+    while True:
+        trace.append(f)
+        hist.append(f)
+        if it >= max_iter:
+            return x, trace, "max_iter", it
+        if stall_window is not None and it >= 2 * stall_window:
+            recent = min(hist[it - stall_window + 1:it + 1])
+            older = min(hist[it - 2 * stall_window + 1:it - stall_window + 1])
+            if recent > ctx.mpf(stall_ratio) * older:
+                return x, trace, "stalled", it
         p = None
         if S:
             q = list(g)
@@ -157,10 +186,14 @@ def lbfgs_mp(fg, x0, nmean, max_iter, history=8, c1=1e-4, step_cap=1e-2, max_hal
                 accepted = True
                 break
             alpha /= 2
+        it += 1
         if not accepted:
             S, Y, R = [], [], []
-            trace.append(f)
+            fails += 1
+            if max_ls_fail is not None and fails >= max_ls_fail:
+                return x, trace, "stalled", it
             continue
+        fails = 0
         ft, gt = fg(xt)
         s = [a - b for a, b in zip(xt, x)]
         y = [a - b for a, b in zip(gt, g)]
@@ -174,8 +207,6 @@ def lbfgs_mp(fg, x0, nmean, max_iter, history=8, c1=1e-4, step_cap=1e-2, max_hal
                 Y.pop(0)
                 R.pop(0)
         x, f, g = xt, ft, gt
-        trace.append(f)
-    return x, trace
 
 
 def fire_mp(fg, x0, nmean, max_iter, step_cap=1e-2):

@@ -79,3 +79,49 @@ def test_quench_reaches_floor_d2_N128():
         mag = float(sk[k]) * N
         bound = (2.0 * np.sqrt(mag) * tol_nk + tol_nk ** 2) / N
         assert abs(mpref.mp_of(e.sk[0, k], e.sk[1, k]) - sk[k]) <= bound
+
+
+# stopping rules: the stall window (W, ratio) and the consecutive line-search
+# failure limit, on settings where each ends the run at a different iteration
+# (the failure cases have isolated failures before the consecutive ones: with
+# limit 1 the run ends earlier than with 2 and 3)
+STOP_CASES = ([dict(stall_window=W, stall_ratio=r) for W, r in [(2, 0.5), (3, 0.1), (4, 0.01), (6, 0.01)]]
+              + [dict(c1=c1, max_halvings=mh, step_cap=sc, max_ls_fail=lf)
+                 for (c1, mh, sc) in [(0.3, 1, 1.0), (1e-4, 0, 0.1)] for lf in (1, 2, 3)])
+
+
+@pytest.mark.parametrize("rules", STOP_CASES)
+def test_stopping_rules_match_256bit(rules):
+    """The oracle's stall window and consecutive-failure stop against the second
+    256-bit implementation of the same rules: the same status at the same
+    iteration, and the same energies along the way."""
+    d, N, R2 = 2, 10, 4
+    n = O.wavevectors(d, R2)
+    pos = inputs.uniform_positions(d, N, 12)
+    fg = mpref.stealthy_fg(n, None, N, d)
+    x0 = [mpref.mp_of(pos[0, a, j], pos[1, a, j]) for a in range(d) for j in range(N)]
+    okw = dict(stall_window=1000)          # no stall-window stop unless the case sets one
+    okw.update(rules)
+    x, res, tr = O.minimize(n, None, pos, trace_cap=200, max_iter=80, s_floor=0.0, **okw)
+    xm, trm, status, iters = mpref.lbfgs_mp_run(fg, x0, mpref.nmean_of(N, d), 80, **rules)
+    assert (res["status"], res["iters"]) == (status, iters) == ("stalled", iters)
+    assert iters < 80
+    for i in range(min(len(trm), res["iters"])):
+        assert abs(mpref.mp_of(*tr[i]) - trm[i]) <= 1e-26 * trm[0], i
+    assert abs(mpref.mp_of(*res["phi"]) - trm[-1]) <= 1e-26 * trm[0]
+
+
+def test_stopping_rule_cases_differ():
+    """The cases above end at different iterations for different limits, so an
+    off-by-one in the window or the failure count would show."""
+    d, N, R2 = 2, 10, 4
+    n = O.wavevectors(d, R2)
+    pos = inputs.uniform_positions(d, N, 12)
+    ends = []
+    for rules in STOP_CASES:
+        okw = dict(stall_window=1000)
+        okw.update(rules)
+        _, res, _ = O.minimize(n, None, pos, max_iter=80, s_floor=0.0, **okw)
+        ends.append(res["iters"])
+    assert len(set(ends[4:7])) == 3 and len(set(ends[7:10])) == 3
+    assert len(set(ends[:4])) >= 3
