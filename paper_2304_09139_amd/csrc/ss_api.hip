@@ -107,6 +107,36 @@ int64_t count_half(int d, int64_t R2) {
   return total;
 }
 
+// Release a plan's device lists and schedules (every pointer may be null).
+void free_plan(Plan* pl) {
+  if (!pl) return;
+  (void)hipFree(pl->lex_n);
+  (void)hipFree(pl->canon_n);
+  (void)hipFree(pl->canon_of_lex);
+  (void)hipFree(pl->runs);
+  (void)hipFree(pl->segs);
+  (void)hipFree(pl->k_of_slot);
+  for (auto& cb : pl->chunk_begin) (void)hipFree(cb.second);
+  for (auto& ns : pl->nk_fixed) {
+    (void)hipFree(ns.second.units);
+    (void)hipFree(ns.second.rows_of);
+  }
+  for (auto& ns : pl->nk_sched) {
+    (void)hipFree(ns.second.units);
+    (void)hipFree(ns.second.rows_of);
+  }
+  (void)hipFree(pl->t2_tiles);
+  (void)hipFree(pl->t2_lexinfo);
+  (void)hipFree(pl->t2_ident);
+  for (auto& ns : pl->nk2_sched) (void)hipFree(ns.second.rows_of);
+  for (auto& ns : pl->nk2_fixed) (void)hipFree(ns.second.rows_of);
+  delete pl;
+}
+
+int build_plan_lists(ss_ctx* ctx, Plan* pl);
+
+// The plan of (d, R2), built and cached on first use.  On failure nothing is
+// cached and everything allocated for it is released.
 int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
   auto key = std::make_pair(d, R2);
   auto it = ctx->plans.find(key);
@@ -119,6 +149,19 @@ int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
   pl->d = d;
   pl->R2 = R2;
   pl->R = (int)isqrt64(R2);
+  const int rc = build_plan_lists(ctx, pl);
+  if (rc != SS_OK) {
+    free_plan(pl);
+    return rc;
+  }
+  ctx->plans[key] = pl;
+  *out = pl;
+  return SS_OK;
+}
+
+int build_plan_lists(ss_ctx* ctx, Plan* pl) {
+  const int d = pl->d;
+  const int64_t R2 = pl->R2;
   SS_HIP(ctx, enumerate(d, R2, pl->R, ctx->build_stream, pl));
   const int64_t M = pl->M;
   std::vector<int32_t> lex((size_t)M * d);
@@ -228,8 +271,6 @@ int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
     SS_HIP(ctx, hipMemcpy(pl->t2_lexinfo, info.data(), sizeof(int32_t) * info.size(), hipMemcpyHostToDevice));
     SS_HIP(ctx, hipMemcpy(pl->t2_ident, ident.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
   }
-  ctx->plans[key] = pl;
-  *out = pl;
   return SS_OK;
 }
 
@@ -652,30 +693,7 @@ int ss_destroy(ss_ctx* ctx) {
   if (!ctx) return SS_OK;
   if (ctx->server) ss_server_stop(ctx);
   hipSetDevice(ctx->device);
-  for (auto& kv : ctx->plans) {
-    Plan* pl = kv.second;
-    hipFree(pl->lex_n);
-    hipFree(pl->canon_n);
-    hipFree(pl->canon_of_lex);
-    hipFree(pl->runs);
-    hipFree(pl->segs);
-    hipFree(pl->k_of_slot);
-    for (auto& cb : pl->chunk_begin) hipFree(cb.second);
-    for (auto& ns : pl->nk_fixed) {
-      hipFree(ns.second.units);
-      hipFree(ns.second.rows_of);
-    }
-    for (auto& ns : pl->nk_sched) {
-      hipFree(ns.second.units);
-      hipFree(ns.second.rows_of);
-    }
-    hipFree(pl->t2_tiles);
-    hipFree(pl->t2_lexinfo);
-    hipFree(pl->t2_ident);
-    for (auto& ns : pl->nk2_sched) hipFree(ns.second.rows_of);
-    for (auto& ns : pl->nk2_fixed) hipFree(ns.second.rows_of);
-    delete pl;
-  }
+  for (auto& kv : ctx->plans) free_plan(kv.second);
   for (auto& v : ctx->prof.ev)
     for (auto& pr : v) {
       hipEventDestroy(pr.a);
@@ -686,6 +704,11 @@ int ss_destroy(ss_ctx* ctx) {
   delete ctx;
   return SS_OK;
 }
+
+#ifndef SS_BUILD_ID
+#define SS_BUILD_ID "unknown"
+#endif
+const char* ss_build_id(void) { return SS_BUILD_ID; }
 
 const char* ss_strerror(int code) {
   switch (code) {

@@ -964,47 +964,52 @@ hipError_t launch_weights(const int32_t* n, int64_t M, int d, int64_t R2, int vk
 }
 
 // Enumerate H(R2): lexicographic list + canonical list + lex -> canonical map.
-// Device buffers are allocated here; M is returned (a synchronising call).
+// Device buffers are allocated here; M is returned (a synchronising call).  The
+// scratch buffers are freed on every path; on failure the plan's lists are left
+// for the caller's plan release (which frees whatever is non-null).
 hipError_t enumerate(int d, int64_t R2, int R, hipStream_t st, Plan* pl) {
   int64_t side = 2 * R + 1, total = 1;
   for (int a = 0; a < d; ++a) total *= side;
   const int64_t nb = (total + kEnumPer - 1) / kEnumPer;
   int32_t *bcount = nullptr, *bofs = nullptr;
   int64_t* dM = nullptr;
-  hipError_t e;
-  if ((e = hipMalloc(&bcount, sizeof(int32_t) * nb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&bofs, sizeof(int32_t) * nb)) != hipSuccess) return e;
-  if ((e = hipMalloc(&dM, sizeof(int64_t))) != hipSuccess) return e;
+  uint64_t* keys = nullptr;
+  hipError_t e = hipSuccess;
+  int64_t M = 0, P2 = 1;
+  unsigned sb = 0;
+  if ((e = hipMalloc(&bcount, sizeof(int32_t) * nb)) != hipSuccess) goto done;
+  if ((e = hipMalloc(&bofs, sizeof(int32_t) * nb)) != hipSuccess) goto done;
+  if ((e = hipMalloc(&dM, sizeof(int64_t))) != hipSuccess) goto done;
   hipLaunchKernelGGL(k_enum_count, dim3((unsigned)nb), dim3(kThreads), 0, st, total, d, R, R2, bcount);
   hipLaunchKernelGGL(k_enum_scan, dim3(1), dim3(1), 0, st, bcount, nb, bofs, dM);
-  int64_t M = 0;
-  if ((e = hipMemcpyAsync(&M, dM, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(&M, dM, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess) goto done;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) goto done;
   pl->M = M;
-  int64_t P2 = 1;
   while (P2 < M) P2 <<= 1;
-  uint64_t* keys = nullptr;
-  if ((e = hipMalloc(&keys, sizeof(uint64_t) * P2)) != hipSuccess) return e;
-  if ((e = hipMalloc(&pl->lex_n, sizeof(int32_t) * M * d)) != hipSuccess) return e;
-  if ((e = hipMalloc(&pl->canon_n, sizeof(int32_t) * M * d)) != hipSuccess) return e;
-  if ((e = hipMalloc(&pl->canon_of_lex, sizeof(int32_t) * M)) != hipSuccess) return e;
+  if ((e = hipMalloc(&keys, sizeof(uint64_t) * P2)) != hipSuccess) goto done;
+  if ((e = hipMalloc(&pl->lex_n, sizeof(int32_t) * M * d)) != hipSuccess) goto done;
+  if ((e = hipMalloc(&pl->canon_n, sizeof(int32_t) * M * d)) != hipSuccess) goto done;
+  if ((e = hipMalloc(&pl->canon_of_lex, sizeof(int32_t) * M)) != hipSuccess) goto done;
   hipLaunchKernelGGL(k_enum_scatter, dim3((unsigned)nb), dim3(kThreads), 0, st, total, d, R, R2, bofs, pl->lex_n,
                      keys);
   if (P2 > M)
     hipLaunchKernelGGL(k_fill_keys, dim3((unsigned)((P2 - M + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
                        keys, M, P2);
-  const unsigned sb = (unsigned)((P2 + kThreads - 1) / kThreads);
+  sb = (unsigned)((P2 + kThreads - 1) / kThreads);
   for (int64_t k = 2; k <= P2; k <<= 1)
     for (int64_t j = k >> 1; j > 0; j >>= 1) hipLaunchKernelGGL(k_bitonic, dim3(sb), dim3(kThreads), 0, st, keys, P2, j, k);
   hipLaunchKernelGGL(k_enum_canon, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, keys, M, d,
                      pl->lex_n, pl->canon_n, pl->canon_of_lex);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  hipFree(keys);
-  hipFree(bcount);
-  hipFree(bofs);
-  hipFree(dM);
-  return hipSuccess;
+  if ((e = hipGetLastError()) != hipSuccess) goto done;
+  e = hipStreamSynchronize(st);
+done:
+  // a launch may still be queued after an early failure: wait before freeing
+  if (e != hipSuccess) (void)hipStreamSynchronize(st);
+  if (keys) (void)hipFree(keys);
+  if (bcount) (void)hipFree(bcount);
+  if (bofs) (void)hipFree(bofs);
+  if (dM) (void)hipFree(dM);
+  return e;
 }
 
 }  // namespace ss

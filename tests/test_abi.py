@@ -28,6 +28,15 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(ss.SIGNATURES)
 
 
+def test_build_id_matches_sources():
+    """libss.so carries the hash of the sources it was built from; a stale
+    binary (sources changed, library not rebuilt) is refused by the binding."""
+    from paper_2304_09139_amd.build import source_hash
+
+    assert ss.build_id() == source_hash()
+    ss.check_build()
+
+
 def test_strerror():
     assert ss.strerror(0) == "ok"
     assert ss.strerror(-1) == "invalid argument"
