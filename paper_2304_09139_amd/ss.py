@@ -37,7 +37,7 @@ class MinOpts(ctypes.Structure):
                 ("stall_window", ctypes.c_int32), ("stall_ratio", ctypes.c_double), ("c1", ctypes.c_double),
                 ("step_cap", ctypes.c_double), ("max_halvings", ctypes.c_int32),
                 ("max_ls_fail", ctypes.c_int32), ("precision", ctypes.c_int32), ("fp64_floor", ctypes.c_double),
-                ("method", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("fault_iter", ctypes.c_int64)]
 
 
 class MinResult(ctypes.Structure):
@@ -57,6 +57,11 @@ class Request(ctypes.Structure):
                 ("opts", MinOpts)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "admitted", "completed", "queued", "running",
+                                               "max_running", "steps", "overtaking")]
+
+
 _V = ctypes.c_void_p
 _I64P = ctypes.POINTER(ctypes.c_int64)
 _SZP = ctypes.POINTER(ctypes.c_size_t)
@@ -65,6 +70,7 @@ _SZP = ctypes.POINTER(ctypes.c_size_t)
 SIGNATURES = {
     "ss_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_V)]),
     "ss_destroy": (ctypes.c_int, [_V]),
+    "ss_build_id": (ctypes.c_char_p, []),
     "ss_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ss_last_error": (ctypes.c_char_p, [_V]),
     "ss_count": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, _I64P]),
@@ -94,10 +100,12 @@ SIGNATURES = {
     "ss_submit": (ctypes.c_int, [_V, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
     "ss_poll": (ctypes.c_int, [_V, ctypes.c_uint64, ctypes.POINTER(MinResult), _V]),
     "ss_server_stop": (ctypes.c_int, [_V]),
+    "ss_server_stats": (ctypes.c_int, [_V, ctypes.c_void_p]),
 }
 
 DEFAULT_MIN_OPTS = dict(history=8, max_iter=100000, s_floor=1e-40, stall_window=50, stall_ratio=0.99, c1=1e-4,
-                        step_cap=1e-2, max_halvings=40, max_ls_fail=3, precision=0, fp64_floor=1e-24, method=0)
+                        step_cap=1e-2, max_halvings=40, max_ls_fail=3, precision=0, fp64_floor=1e-24, method=0,
+                        fault_iter=0)
 PRECISION = {"dd": 0, "fp64": 1, "staged": 2}
 METHOD = {"lbfgs": 0, "fire": 1}
 
@@ -116,6 +124,22 @@ def lib():
                 fn.argtypes = args
         _LIB = L
     return _LIB
+
+
+def build_id() -> str:
+    """The source hash libss.so was compiled from (ss_build_id)."""
+    return lib().ss_build_id().decode()
+
+
+def check_build() -> None:
+    """Raise if libss.so was not built from the sources next to it (a stale
+    binary would silently run other kernels than the tree holds)."""
+    from .build import source_hash
+
+    have, want = build_id(), source_hash()
+    if have != want:
+        raise RuntimeError(f"{LIB_PATH} was built from sources {have}, the tree holds {want}: rebuild it with "
+                           f"paper_2304_09139_amd.build.build()")
 
 
 def strerror(code: int) -> str:
@@ -154,6 +178,31 @@ def cutoff(d: int, N: int, chi: float) -> tuple[int, int]:
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, device, dtype, shape, name: str):
+    """Check a tensor handed to the library as a raw device pointer: on the
+    context's device, of the expected dtype and shape, and contiguous (a host
+    pointer would fault the GPU; another dtype or layout would be misread)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the context is on {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _need_problem(ctx, w, n, v, pos):
+    dev = ctx.device
+    _need(n, dev, torch.int32, (w.M, w.d), "wavevectors n")
+    if v is not None:
+        _need(v, dev, torch.float64, (2, w.M), "weights v")
+    _need(pos, dev, torch.float64, (2, w.d, w.N), "positions")
 
 
 def _stream(device):
@@ -206,6 +255,7 @@ class Context:
         in tiles.json next to this module, if present) or a list of entries."""
         if not torch.cuda.is_available():
             raise RuntimeError("libss needs a HIP device; none is visible")
+        check_build()
         self.device = torch.device("cuda", device)
         self._h = ctypes.c_void_p()
         _check(lib().ss_create(device, ctypes.byref(self._h)), what="ss_create")
@@ -260,6 +310,7 @@ class Context:
         return n
 
     def weights(self, w: Workload, n: torch.Tensor) -> torch.Tensor:
+        _need(n, self.device, torch.int32, (w.M, w.d), "wavevectors n")
         v = torch.empty((2, w.M), dtype=torch.float64, device=self.device)
         p = w.problem()
         self._chk(lib().ss_weights(self._h, ctypes.byref(p), _ptr(n), _ptr(v), _stream(self.device)),
@@ -291,6 +342,10 @@ class Context:
             o["grad"] = torch.empty((2, w.d, w.N), dtype=torch.float64, device=dev)
         if nk and "nk" not in o:
             o["nk"] = torch.empty((4, w.M), dtype=torch.float64, device=dev)
+        _need_problem(self, w, n, v, pos)
+        for k, shape in (("phi", (2,)), ("smax", (2,)), ("grad", (2, w.d, w.N)), ("nk", (4, w.M))):
+            if k in o and o[k] is not None:
+                _need(o[k], dev, torch.float64, shape, f"output {k}")
         ws = self.workspace(w, 0)
         p = w.problem()
         fn = lib().ss_energy_grad_fp64 if fp64 else lib().ss_energy_grad
@@ -303,6 +358,7 @@ class Context:
     def minimize(self, w: Workload, n: torch.Tensor, v: torch.Tensor | None, pos: torch.Tensor,
                  **opts) -> dict:
         """L-BFGS quench of pos (updated in place, [2, d, N]) on the device."""
+        _need_problem(self, w, n, v, pos)
         mo = _min_opts(opts)
         res = MinResult()
         ws = self.workspace(w, 1)
@@ -346,6 +402,13 @@ class Context:
         n = len(works)
         if len(positions) != n:
             raise ValueError("one position tensor per workload")
+        if weights is not None and len(weights) != n:
+            raise ValueError("one weight entry (tensor or None) per workload")
+        for i, (w, x) in enumerate(zip(works, positions)):
+            _need(x, self.device, torch.float64, (2, w.d, w.N), f"positions[{i}]")
+            wt = None if weights is None else weights[i]
+            if wt is not None:
+                _need(wt, self.device, torch.float64, (2, w.M), f"weights[{i}]")
         if opts is None or isinstance(opts, dict):
             o = dict(DEFAULT_MIN_OPTS)
             o.update(opts or {})
@@ -360,13 +423,16 @@ class Context:
         need = self.batch_workspace_size(works, opts_list)
         if ws is None:
             ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        elif ws.device != self.device or not ws.is_contiguous():
+            raise ValueError(f"the batch workspace must be a contiguous tensor on {self.device}")
         pos_arr = (_V * n)(*[p.data_ptr() for p in positions])
         v_arr = None
         if weights is not None:
             v_arr = (_V * n)(*[(v.data_ptr() if v is not None else None) for v in weights])
         res = (MinResult * n)()
-        self._chk(lib().ss_minimize_batch(self._h, n, probs, v_arr, pos_arr, mos, res, _ptr(ws), ws.numel(),
-                                          _stream(self.device)), "ss_minimize_batch")
+        self._chk(lib().ss_minimize_batch(self._h, n, probs, v_arr, pos_arr, mos, res, _ptr(ws),
+                                          ws.numel() * ws.element_size(), _stream(self.device)),
+                  "ss_minimize_batch")
         return [_result(r) for r in res]
 
     # ---- serving -----------------------------------------------------------------
@@ -408,6 +474,12 @@ class Context:
         self._chk(rc, "ss_poll")
         del self._served[ticket]
         return _result(res), out
+
+    def server_stats(self) -> dict:
+        """Counters of the running server (ss_server_stats)."""
+        st = ServerStats()
+        self._chk(lib().ss_server_stats(self._h, ctypes.byref(st)), "ss_server_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
     def server_stop(self) -> None:
         rc = lib().ss_server_stop(self._h)
