@@ -83,6 +83,12 @@ int ss_create(int device, ss_ctx** out);
 /* Release the context and its plans.  NULL is accepted. */
 int ss_destroy(ss_ctx* ctx);
 
+/* Build id of this library: the first 16 hex digits of the SHA-256 of the
+ * sources it was compiled from (HIP sources and headers, and this header), so
+ * that a caller can check that a binary matches its source tree.  Static
+ * string; "unknown" if the build did not define it. */
+const char* ss_build_id(void);
+
 /* Static description of a return code. */
 const char* ss_strerror(int code);
 
@@ -203,7 +209,12 @@ int ss_profile_read(ss_ctx* ctx, int kernel, int reset, int64_t* launches, doubl
  * then dt <- dt / 2, v <- 0, a <- 0.1; then v <- v + dt F, x <- x + dt v.
  * dt0^2 max|g(x0)| = step_cap N^(-1/d), dt_max = 10 dt0.  history, c1,
  * max_halvings and max_ls_fail do not apply; the stopping rules are the same
- * (FIRE's energy is not monotone, so a longer stall_window suits it). */
+ * (FIRE's energy is not monotone, so a longer stall_window suits it).
+ * fault_iter is a failure-injection hook for testing that a configuration
+ * whose energy turns non-finite ends on its own (status 3) while every other
+ * configuration of a batch or server runs on unaffected: when > 0, the first
+ * trial point of iteration fault_iter (counted from 1 within the running
+ * stage) gets a NaN coordinate.  0 disables it; production runs leave it 0. */
 typedef struct {
   int32_t history;      /* 1..16 (8 is typical)                 */
   int64_t max_iter;     /* >= 0                                 */
@@ -217,6 +228,7 @@ typedef struct {
   int32_t precision;    /* 0 double-double, 1 FP64, 2 staged    */
   double fp64_floor;    /* >= 0: S_max floor of the FP64 stage (e.g. 1e-24) */
   int32_t method;       /* 0 L-BFGS, 1 FIRE                     */
+  int64_t fault_iter;   /* failure injection, 0 = off (see above) */
 } ss_min_opts;
 
 /* status: 0 converged (S_max <= s_floor), 1 stalled, 2 iteration cap,
@@ -297,8 +309,11 @@ int ss_minimize_batch(ss_ctx* ctx, int count, const ss_problem* probs, const dou
  * A server on a context runs a worker thread with its own HIP stream that
  * keeps one batched minimiser step in flight over every configuration it is
  * running.  Requests wait in submission order; at step boundaries the worker
- * admits as many as there are free slots and room in the caller's device
- * arena (first fit), runs their starting evaluation, and adds them to the work
+ * walks the queue and admits every request for which there are a free slot and
+ * room in the caller's device arena (first fit), so a request too large for
+ * the space free now does not hold back smaller ones behind it -- until 16
+ * admissions have overtaken it, after which nothing else is admitted ahead of
+ * it.  Admitted requests get their starting evaluation and join the work
  * lists; stopped configurations are copied out and their slot and arena space
  * reused.  Launch shapes come from the tile table by (d, N, M) alone, so a
  * request's result is bitwise the same whatever else is being served and equal
@@ -330,8 +345,8 @@ int ss_uniform_positions(int d, int64_t N, uint64_t seed, double* pos_host_out);
 
 /* Start the server.  arena_dev: caller-owned device memory that holds every
  * running configuration's workspace (ss_batch_workspace_size of a single
- * problem gives the order of magnitude; a request that cannot fit even in
- * an empty arena fails with SS_ENOMEM at ss_poll); max_slots: the most
+ * problem gives the order of magnitude; ss_submit refuses a request larger
+ * than the whole arena with SS_ENOMEM); max_slots: the most
  * configurations run at once (1..65536).  The server also allocates its
  * descriptor arrays and work lists (a few MB).  SS_ESTATE if one already runs
  * on this context. */
@@ -340,17 +355,34 @@ int ss_server_start(ss_ctx* ctx, void* arena_dev, size_t arena_bytes, int max_sl
 /* Queue one request; *ticket identifies it for ss_poll.  Non-blocking apart
  * from building the wavevector plan of a new (d, R2) on first use.  SS_EINVAL
  * for an invalid request (shape, vkind, options, non-finite positions),
- * SS_ESTATE without a running server or while it stops, or the server's error
- * after a failure. */
+ * SS_ENOMEM for a request whose workspace, positions and weights exceed the
+ * whole arena (detail in ss_last_error), SS_ESTATE without a running server or
+ * while it stops, or the server's error after a failure. */
 int ss_submit(ss_ctx* ctx, const ss_request* req, uint64_t* ticket);
 
 /* SS_PENDING while the request is queued or running.  When it is done: fills
  * *out (seconds = from ss_submit until the result was copied out), copies the
  * final positions to pos_host_out (double[2][d][N], if not NULL), forgets the
- * ticket and returns SS_OK (the quench's own outcome is out->status).
- * SS_ENOTFOUND for an unknown or already collected ticket; a failed request
- * returns its error (SS_ENOMEM: larger than the arena). */
+ * ticket and returns SS_OK (the quench's own outcome is out->status: a
+ * configuration whose energy turned non-finite ends with status 3 and the
+ * others run on).  SS_ENOTFOUND for an unknown or already collected ticket; a
+ * request failed by a server error returns that error. */
 int ss_poll(ss_ctx* ctx, uint64_t ticket, ss_min_result* out, double* pos_host_out);
+
+/* Counters of a running server (a snapshot). */
+typedef struct {
+  int64_t submitted;   /* requests accepted by ss_submit                              */
+  int64_t admitted;    /* requests that have started running                           */
+  int64_t completed;   /* results ready (collected or not)                             */
+  int64_t queued;      /* waiting now                                                  */
+  int64_t running;     /* configurations in the batched steps now                      */
+  int64_t max_running; /* the most configurations running at once so far               */
+  int64_t steps;       /* batched minimiser steps launched                             */
+  int64_t overtaking;  /* admissions that went ahead of an older request still waiting */
+} ss_server_counters;
+
+/* Fill *out with the server's counters.  SS_ESTATE without a running server. */
+int ss_server_stats(ss_ctx* ctx, ss_server_counters* out);
 
 /* Stop accepting requests, finish every queued and running one, stop the
  * worker and release the server; results not yet collected with ss_poll are

@@ -17,7 +17,10 @@
 //    representation of Byrd, Nocedal & Schnabel (Math. Prog. 63, 1994,
 //    Thm 2.2), algebraically identical to the two-loop recursion of Nocedal &
 //    Wright (Alg. 7.4) that the oracle uses; when the history is empty or
-//    g.p >= 0, the history is cleared and p = -g step_cap N^(-1/d) / max|g|;
+//    g.p >= 0, the history is cleared and
+//    p = -g min(step_cap N^(-1/d) / max|g|, 2 Phi / g.g): at most step_cap of the
+//    mean spacing, and no longer than the step to the minimum (value 0, a
+//    ground state) of the isotropic quadratic through (Phi, g);
 //  * Armijo backtracking from alpha = 1 by halving, accept when
 //    Phi(x + alpha p) <= Phi(x) + c1 alpha g.p; after max_halvings halvings a
 //    failure is recorded, the history cleared and x kept;
@@ -207,7 +210,9 @@ __device__ __forceinline__ void step_body(const VecSet& V, const MinState* S_, i
     p = vload(V.p, nv, i);
   }
   const double a = S.alpha;
-  const dd r = dd_add(vload(V.x, nv, i), dd{a * p.h, a * p.l});
+  dd r = dd_add(vload(V.x, nv, i), dd{a * p.h, a * p.l});
+  // failure injection: the first trial of iteration fault_iter gets a NaN
+  if (i == 0 && S.fault_iter > 0 && S.iter + 1 == S.fault_iter && S.halvings == 0) r.h = __builtin_nan("");
   V.xt[i] = r.h;
   V.xt[nv + i] = r.l;
 }
@@ -279,6 +284,7 @@ __device__ __forceinline__ void init_body(MinState* S_, const MinParams& P, int 
     S.alpha = 1.0;
     S.running = 1;
     S.status = 2;
+    S.fault_iter = P.fault_iter;
   }
   const dd f = ld(S.f), smax = ld(S.smax);  // written by the previous kernel
   if (!isfinite(f.h)) {
@@ -679,7 +685,9 @@ __global__ void __launch_bounds__(kThreads) k_fire_step(VecSet V, const MinState
   dd v{0.0, 0.0};
   if (!S.fire_reset) v = dd_sub(dd_mul(ld(S.fcv), vload(V.p, nv, i)), dd_mul(ld(S.fcg), g));
   v = dd_sub(v, dd_mul_d(g, dt));
-  const dd x = dd_add(vload(V.x, nv, i), dd_mul_d(v, dt));
+  dd x = dd_add(vload(V.x, nv, i), dd_mul_d(v, dt));
+  // failure injection: the step of iteration fault_iter gets a NaN
+  if (i == 0 && S.fault_iter > 0 && S.iter + 1 == S.fault_iter) x.h = __builtin_nan("");
   V.p[i] = v.h;
   V.p[nv + i] = v.l;
   V.x[i] = x.h;
@@ -914,7 +922,7 @@ bool min_opts_valid(const ss_min_opts* op) {
   return op && op->history >= 1 && op->history <= kMaxHistory && op->max_iter >= 0 && op->stall_window >= 1 &&
          op->stall_window <= kMaxWindow && op->max_halvings >= 0 && op->max_ls_fail >= 1 && op->step_cap > 0.0 &&
          op->c1 > 0.0 && op->c1 < 1.0 && op->stall_ratio > 0.0 && op->precision >= 0 && op->precision <= 2 &&
-         op->fp64_floor >= 0.0 && op->method >= 0 && op->method <= 1;
+         op->fp64_floor >= 0.0 && op->method >= 0 && op->method <= 1 && op->fault_iter >= 0;
 }
 
 MinParams min_params(const ss_min_opts* op, const ss_problem* prob) {
@@ -928,6 +936,7 @@ MinParams min_params(const ss_min_opts* op, const ss_problem* prob) {
   P.stall_ratio = op->stall_ratio;
   P.c1 = op->c1;
   P.step = op->step_cap * pow((double)prob->N, -1.0 / (double)prob->d);
+  P.fault_iter = op->fault_iter;
   return P;
 }
 

@@ -38,12 +38,14 @@ struct MinState {
   double fdt, fdt_max, fa;
   int32_t npos, fire_reset;
   double fcv[2], fcg[2];  // this step's velocity mixing coefficients
+  int64_t fault_iter;     // > 0: the trial of this iteration gets a NaN (failure injection)
 };
 
 struct MinParams {
   int32_t m, W, max_halvings, max_ls_fail;
   int64_t max_iter;
   double s_floor, stall_ratio, c1, step;  // step = step_cap * N^(-1/d)
+  int64_t fault_iter;                     // failure injection (ss_min_opts), 0 = off
 };
 
 // the vectors of one quench

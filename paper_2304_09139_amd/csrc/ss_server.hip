@@ -2,10 +2,13 @@
 //
 // A worker thread owns one stream and keeps one batched minimiser step in
 // flight for every configuration it is running (the batched launches of
-// ss_batch.hip).  Requests wait in a FIFO queue; at every step boundary the
-// worker admits as many as there are free slots and arena space (first fit
-// over the caller's device arena), runs their starting evaluation, and adds
-// them to the work lists; configurations that stop are copied out (positions
+// ss_batch.hip).  Requests wait in submission order; at every step boundary the
+// worker walks the queue and admits every request for which there are a free
+// slot and arena space (first fit over the caller's device arena), so a large
+// request that does not fit yet does not hold back smaller ones behind it --
+// until it has been overtaken kMaxOvertake times, after which nothing else is
+// admitted before it (no starvation).  Admitted requests get their starting
+// evaluation and join the work lists; configurations that stop are copied out (positions
 // and final state, through pinned memory) and their slot and arena space are
 // reused.  Each configuration's launch shape comes from the tile table by
 // (d, N, M) alone, so a request's result is bitwise the same whatever else is
@@ -39,6 +42,9 @@ using namespace eng;
 using Clock = std::chrono::steady_clock;
 
 constexpr int kDepth = 3;  // minimiser steps in flight
+// admissions that may overtake the oldest queued request before the worker
+// admits nothing else ahead of it
+constexpr int kMaxOvertake = 16;
 
 // first-fit allocator of byte ranges of the arena, coalescing on release
 class RangeAlloc {
@@ -94,7 +100,17 @@ struct Request {
   void* pin = nullptr;  // pinned copy-out buffer: positions then MinState
   hipEvent_t done_ev = nullptr;
   int64_t iters64 = 0, evals64 = 0;  // a staged quench's FP64 stage
+  size_t need = 0;      // arena bytes: workspace, positions and weights
+  int overtaken = 0;    // admissions that went ahead of it while it waited
 };
+
+// arena bytes of one served configuration: its workspace, its positions and
+// (weighted) its weight table
+size_t request_bytes(const eng::HostSlot& h, const ss_problem& p) {
+  const size_t vec = eng::al256(sizeof(double) * 2 * (size_t)h.nv);
+  const size_t wbytes = p.vkind ? eng::al256(sizeof(double) * 2 * (size_t)p.M) : 0;
+  return h.bytes + vec + wbytes;
+}
 
 struct InFlight {
   hipEvent_t ev;
@@ -118,6 +134,7 @@ struct ss_server {
   std::string error_msg;
   uint64_t next_ticket = 1;
   std::deque<std::shared_ptr<ss::Request>> queue;
+  ss_server_counters stats{};  // counters (under mu)
   std::map<uint64_t, std::shared_ptr<ss::Request>> tickets;
   // worker-owned
   hipStream_t st = nullptr;
@@ -241,42 +258,35 @@ class Worker {
 
   DevArrays dev() const { return DevArrays{S->d_es, S->d_ms, S->d_units, S->d_list, S->d_flags}; }
 
-  // take queued requests while slots and arena space last (FIFO)
+  // admit queued requests in submission order while slots last: each one whose
+  // arena range fits now is taken; one that does not fit is passed over, unless
+  // it is the oldest and has already been overtaken kMaxOvertake times
   int admit() {
+    std::vector<std::shared_ptr<Request>> waiting;
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      waiting.assign(S->queue.begin(), S->queue.end());
+    }
     std::vector<int> admitted;
-    for (;;) {
-      std::shared_ptr<Request> r;
-      {
-        std::lock_guard<std::mutex> g(S->mu);
-        if (S->queue.empty() || S->free_slots.empty()) break;
-        r = S->queue.front();
-      }
+    std::vector<std::shared_ptr<Request>> taken;
+    std::vector<Request*> passed;  // waiting requests this scan went past
+    int64_t overtook = 0;          // admissions that went ahead of a waiting request
+    for (auto& r : waiting) {
+      if (S->free_slots.empty()) break;
       const HostSlot& h = r->h;
-      int rc = SS_OK;
-      const size_t vec = al256(sizeof(double) * 2 * (size_t)h.nv);
-      const size_t wbytes = r->prob.vkind ? al256(sizeof(double) * 2 * (size_t)r->prob.M) : 0;
-      const size_t need = h.bytes + vec + wbytes;
       size_t off = 0;
-      if (rc == SS_OK && !S->ranges.alloc(need, &off)) {
-        if (S->active.empty() && admitted.empty() && S->copying.empty()) {
-          rc = SS_ENOMEM;  // cannot fit even in an empty arena
-        } else {
-          break;  // wait for space
-        }
+      if (!S->ranges.alloc(r->need, &off)) {
+        passed.push_back(r.get());
+        if (r->overtaken >= kMaxOvertake) break;  // reserve the arena for it
+        continue;
       }
-      {
-        std::lock_guard<std::mutex> g(S->mu);
-        S->queue.pop_front();
-        if (rc != SS_OK) {
-          r->state = 4;
-          r->rc = rc;
-          S->cv.notify_all();
-          continue;
-        }
-      }
+      for (Request* p : passed) p->overtaken += 1;
+      if (!passed.empty()) ++overtook;
+      taken.push_back(r);
       const int slot = S->free_slots.back();
       S->free_slots.pop_back();
       char* mem = S->arena + off;
+      const size_t vec = al256(sizeof(double) * 2 * (size_t)h.nv);
       double* x = (double*)(mem + h.bytes);
       double* v = r->prob.vkind ? (double*)(mem + h.bytes + vec) : nullptr;
       // descriptors staged in this slot's pinned cell: its previous upload was
@@ -293,23 +303,38 @@ class Worker {
       S->slot_gen[slot] += 1;
       r->slot = slot;
       r->off = off;
-      r->bytes = need;
-      {
-        std::lock_guard<std::mutex> g(S->mu);
-        r->state = 1;
-      }
+      r->bytes = r->need;
       admitted.push_back(slot);
     }
     if (admitted.empty()) return SS_OK;
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      for (auto& r : taken) {
+        r->state = 1;
+        S->queue.erase(std::find(S->queue.begin(), S->queue.end(), r));
+      }
+      S->stats.admitted += (int64_t)taken.size();
+      S->stats.overtaking += overtook;
+      S->stats.queued = (int64_t)S->queue.size();
+    }
     int rc = upload_lists(admitted);
     if (rc) return rc;
     W_HIP(launch_start(S->ctx, dev(), L, st));
     for (int s : admitted) S->active.push_back(s);
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->stats.running = (int64_t)S->active.size();
+      if (S->stats.running > S->stats.max_running) S->stats.max_running = S->stats.running;
+    }
     return upload_lists(S->active);
   }
 
   int enqueue_tick() {
     W_HIP(launch_tick(S->ctx, dev(), L, st));
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->stats.steps += 1;
+    }
     const int q = (int)(tick % kDepth);
     SlotFlags* hf = S->h_flags + (size_t)q * S->max_slots;
     W_HIP(hipMemcpyAsync(hf, S->d_flags, sizeof(SlotFlags) * S->max_slots, hipMemcpyDeviceToHost, st));
@@ -388,6 +413,7 @@ class Worker {
     {
       std::lock_guard<std::mutex> g(S->mu);
       r->state = 2;
+      S->stats.running = (int64_t)S->active.size();
     }
     // later work on this stream runs after the copies: the slot and the range
     // can be handed out at once
@@ -435,6 +461,7 @@ class Worker {
         r->res.evals_fp64 = all64 ? ms.evals : r->evals64;
         r->res.seconds = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
         r->state = 3;
+        S->stats.completed += 1;
         S->cv.notify_all();
       }
       S->copying.erase(S->copying.begin() + i);
@@ -564,6 +591,12 @@ extern "C" int ss_submit(ss_ctx* ctx, const ss_request* req, uint64_t* ticket) {
   r->opts = req->opts;
   rc = eng::setup_slot(ctx, &p, &req->opts, &r->h);
   if (rc) return rc;
+  r->need = request_bytes(r->h, p);
+  if (r->need > S->arena_bytes) {
+    ctx->last_error = "request needs " + std::to_string(r->need) + " arena bytes, the server arena holds " +
+                      std::to_string(S->arena_bytes);
+    return SS_ENOMEM;
+  }
   if (req->pos_host) {
     r->pos.assign(req->pos_host, req->pos_host + (size_t)2 * p.d * p.N);
   } else {
@@ -589,6 +622,8 @@ extern "C" int ss_submit(ss_ctx* ctx, const ss_request* req, uint64_t* ticket) {
   r->ticket = S->next_ticket++;
   S->tickets[r->ticket] = r;
   S->queue.push_back(r);
+  S->stats.submitted += 1;
+  S->stats.queued = (int64_t)S->queue.size();
   *ticket = r->ticket;
   S->cv.notify_all();
   return SS_OK;
@@ -614,6 +649,18 @@ extern "C" int ss_poll(ss_ctx* ctx, uint64_t ticket, ss_min_result* out, double*
   }
   if (out) *out = r->res;
   if (pos_host_out) memcpy(pos_host_out, r->pos.data(), sizeof(double) * r->pos.size());
+  return SS_OK;
+}
+
+extern "C" int ss_server_stats(ss_ctx* ctx, ss_server_counters* out) {
+  if (!ctx || !out) return SS_EINVAL;
+  ss_server* S = ctx->server;
+  if (!S) {
+    ctx->last_error = "no server is running";
+    return SS_ESTATE;
+  }
+  std::lock_guard<std::mutex> g(S->mu);
+  *out = S->stats;
   return SS_OK;
 }
 
