@@ -181,12 +181,23 @@ def test_deterministic(ctx):
 
 
 def test_invalid_arguments(ctx):
+    import ctypes
+
     d, N = 2, 50
     R2, M = ss.cutoff(d, N, 0.3)
     n = ctx.wavevectors(d, R2)
     pos = dev(inputs.uniform_positions(d, N, 1))
+    phi = torch.empty(2, dtype=torch.float64, device="cuda")
+    ws = ctx.workspace(ss.Workload(d, N, R2, M), 0)
+    # the C interface rejects an inconsistent problem before any launch
     for bad in [ss.Workload(d, N, R2, M + 1), ss.Workload(5, N, R2, M), ss.Workload(d, 0, R2, M),
                 ss.Workload(d, N, R2, M, L=-1.0), ss.Workload(d, N, R2, M, vkind=1)]:
+        p = bad.problem()
+        rc = ss.lib().ss_energy_grad(ctx._h, ctypes.byref(p), ss._ptr(n), None, ss._ptr(pos), ss._ptr(phi), None,
+                                     None, None, ss._ptr(ws), ws.numel(), None)
+        assert rc == ss.SS_EINVAL, bad
+    # so does the binding (through the same C checks)
+    for bad in [ss.Workload(d, N, R2, M, L=-1.0), ss.Workload(d, N, R2, M, vkind=1)]:
         with pytest.raises(ss.SSError) as e:
             ctx.energy_grad(bad, n, None, pos)
         assert e.value.code == ss.SS_EINVAL
@@ -194,11 +205,23 @@ def test_invalid_arguments(ctx):
     w = ss.Workload(d, N, R2, M)
     p = w.problem()
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
-    phi = torch.empty(2, dtype=torch.float64, device="cuda")
-    import ctypes
     rc = ss.lib().ss_energy_grad(ctx._h, ctypes.byref(p), ss._ptr(n), None, ss._ptr(pos), ss._ptr(phi), None,
                                  None, None, ss._ptr(small), 16, None)
     assert rc == ss.SS_EINVAL
+    # the binding refuses tensors the library would misread or fault on: host
+    # memory, another dtype, a non-contiguous view, a shape that does not match
+    # the problem
+    host = torch.from_numpy(inputs.uniform_positions(d, N, 1))
+    for bad_pos in (host, pos.float(), pos.transpose(1, 2).contiguous().transpose(1, 2),
+                    dev(inputs.uniform_positions(d, N + 1, 1))):
+        with pytest.raises(ValueError):
+            ctx.energy_grad(w, n, None, bad_pos)
+    with pytest.raises(ValueError):
+        ctx.energy_grad(w, n.cpu(), None, pos)
+    with pytest.raises(ValueError):
+        ctx.minimize(w, n, None, host)
+    with pytest.raises(ValueError):
+        ctx.minimize_batch([w], [host])
     # a cutoff whose particle table (d (R + 1) dd complex entries) exceeds the
     # 64 KB LDS tile of the piece walk is rejected: d = 1, R = 2048
     R2b = 2048 * 2048
@@ -209,13 +232,14 @@ def test_invalid_arguments(ctx):
     assert e.value.code == ss.SS_EINVAL
 
 
-@pytest.mark.parametrize("d,N,chi,vkind,cfg,nk_samples,grad_samples",
-                         [(3, 8000, 0.45, 0, 2, 32, 12), (3, 30000, 0.45, 1, 4, 32, 8)])
-def test_full_size_sampled(ctx, d, N, chi, vkind, cfg, nk_samples, grad_samples):
+@pytest.mark.parametrize("d,N,chi,vkind,cfg,grad_samples",
+                         [(3, 8000, 0.45, 0, 2, 256), (3, 30000, 0.45, 1, 4, 256)])
+def test_full_size(ctx, d, N, chi, vkind, cfg, grad_samples):
     """The d=3, N=8000, chi=0.45 and the weighted d=3, N=30000, chi=0.45
     evaluations at full size, in the launch shape the benchmark times: n~ at
-    sampled k and the gradient at sampled particles against the oracle (which
-    needs all n~ for the gradient, computed on the host cores)."""
+    every wavevector, Phi, and the gradient at sampled particles (the first,
+    the last and random ones) against the oracle (which needs all n~ for the
+    gradient, computed on the host cores)."""
     R2, M = ss.cutoff(d, N, chi)
     w = ss.Workload(d, N, R2, M, 1.0, vkind)
     pos = inputs.config_positions(cfg, d, N, 0)
@@ -226,20 +250,21 @@ def test_full_size_sampled(ctx, d, N, chi, vkind, cfg, nk_samples, grad_samples)
     n = host(n_t)
     v = O.weights(n, R2, vkind) if vkind else None
     rng = np.random.default_rng(0)
-    ks = np.unique(np.concatenate([[0, M - 1], rng.choice(M, nk_samples, replace=False)]))
-    ref_nk = O.nk(n, pos)                     # all k: needed by the gradient
-    dC = np.abs(dd_diff(got["nk"][0, ks], got["nk"][1, ks], ref_nk[0, ks], ref_nk[1, ks]))
-    dS = np.abs(dd_diff(got["nk"][2, ks], got["nk"][3, ks], ref_nk[2, ks], ref_nk[3, ks]))
+    ref_nk = O.nk(n, pos)                     # all k
+    dC = np.abs(dd_diff(got["nk"][0], got["nk"][1], ref_nk[0], ref_nk[1]))
+    dS = np.abs(dd_diff(got["nk"][2], got["nk"][3], ref_nk[2], ref_nk[3]))
     assert dC.max() <= TOL * N and dS.max() <= TOL * N
     e = O.energy_from_nk(N, v, ref_nk)
     assert abs(dd_diff(got["phi"][0], got["phi"][1], e.phi[0], e.phi[1])) <= TOL * e.phi[0]
+    assert abs(dd_diff(got["smax"][0], got["smax"][1], e.smax[0], e.smax[1])) <= TOL * e.smax[0]
     js = np.unique(np.concatenate([[0, N - 1], rng.choice(N, grad_samples, replace=False)]))
+    assert len(js) >= 256
     g = O.grad(n, v, pos, ref_nk, js=js)      # [nj, d, 2]
     G = grad_scale(n, v, ref_nk)
-    for q, j in enumerate(js):
-        for a in range(d):
-            diff = abs(dd_diff(got["grad"][0, a, j], got["grad"][1, a, j], g[q, a, 0], g[q, a, 1]))
-            assert diff <= TOL * G[a]
+    dg = np.abs(dd_diff(got["grad"][0][:, js].T, got["grad"][1][:, js].T, g[:, :, 0], g[:, :, 1]))  # [nj, d]
+    assert np.all(dg <= TOL * G[None, :]), (dg / G[None, :]).max()
+    print(f"d={d} N={N}: max|dn~|/N = {max(dC.max(), dS.max()) / N:.2e}, max|dg|/G = {(dg / G[None, :]).max():.2e} "
+          f"over {len(js)} particles")
     # translation invariance at full size: sum_j dPhi/dr_j = 0
     tot = got["grad"][0].sum(axis=1) + got["grad"][1].sum(axis=1)
     assert np.all(np.abs(tot) <= 1e-12 * G)

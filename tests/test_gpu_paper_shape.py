@@ -4,8 +4,10 @@ pairs, a 65 GB phase table in HBM).
 
 The oracle cannot sum every pair at this size in a test's time, so the checks
 are: n~ at sampled wavevectors (the smallest |k|, the outermost shell and
-others) against the oracle to |dC|, |dS| <= 1e-26 N; translation invariance of
-the gradient (sum_j dPhi/dr_j = 0, the total force on the system); and two
+others) against the oracle to |dC|, |dS| <= 1e-26 N; the gradient of 16
+sampled particles against the oracle's gradient pass fed the GPU's n~ (all M
+wavevectors per particle) to |dg| <= 1e-26 G; translation invariance of the
+gradient (sum_j dPhi/dr_j = 0, the total force on the system); and two
 evaluations giving the same bits.
 """
 import numpy as np
@@ -42,10 +44,20 @@ def test_d2_N2e6_chi01_evaluation():
         dC = np.abs((got["nk"][0, ks] - ref[0]) + (got["nk"][1, ks] - ref[1]))
         dS = np.abs((got["nk"][2, ks] - ref[2]) + (got["nk"][3, ks] - ref[3]))
         assert dC.max() <= TOL * N and dS.max() <= TOL * N, (dC.max() / N, dS.max() / N)
+        # the gradient pass at 16 particles: the oracle's sum over all M
+        # wavevectors with the GPU's n~ (the n~ pass is checked above)
+        js = np.array([0, 1, 2, 12345, 499999, 1000000, 1000001, 1333333, 1500000, 1700001, 1800000, 1900000,
+                       1999997, 1999998, 1999999, 777777])
+        gref = O.grad(n, None, pos, got["nk"], js=js)          # [16, d, 2]
+        nkabs = np.abs(got["nk"][0]) + np.abs(got["nk"][2])
+        G = 4 * np.pi * (np.abs(n).T.astype(np.float64) @ nkabs)   # [d]
+        dg = np.abs((got["grad"][0][:, js].T - gref[:, :, 0]) + (got["grad"][1][:, js].T - gref[:, :, 1]))
+        assert np.all(dg <= TOL * G[None, :]), (dg / G[None, :]).max()
         g = got["grad"]
         tot = np.abs(g[0].sum(axis=1) + g[1].sum(axis=1))
         assert np.all(tot <= 1e-12 * np.abs(g[0]).sum(axis=1)), tot
-        print(f"d=2 N=2e6 chi=0.1: max|dn~|/N = {max(dC.max(), dS.max()) / N:.2e}, |sum_j g| = {tot}")
+        print(f"d=2 N=2e6 chi=0.1: max|dn~|/N = {max(dC.max(), dS.max()) / N:.2e}, "
+              f"max|dg|/G = {(dg / G[None, :]).max():.2e} at 16 particles, |sum_j g| = {tot}")
     finally:
         ctx.close()
         torch.cuda.empty_cache()
