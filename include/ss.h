@@ -294,8 +294,11 @@ int ss_batch_workspace_size(ss_ctx* ctx, int count, const ss_problem* probs, con
  * place; v_dev[i] is the weight table double[2][M_i] for vkind != 0 (v_dev may
  * be NULL when every vkind is 0).  The wavevector sets are built internally
  * from (d_i, R2_i).  ws: ss_batch_workspace_size bytes of device memory.
- * Batched quenches run L-BFGS (method 0) at any precision; a staged
- * configuration switches to double-double on its own when its FP64 stage stops.
+ * Batched quenches run L-BFGS or FIRE (method 0 or 1, mixed freely) at any
+ * precision; a staged configuration switches to double-double on its own when
+ * its FP64 stage stops.  A FIRE configuration takes the same steps as under
+ * ss_minimize (its time step is derived on the device from max|g(x0)| with the
+ * same IEEE operations).
  * Synchronising: returns when every quench has stopped, with out[i] filled;
  * out[i].seconds is the time from the call until the library saw quench i
  * stop.  Returns SS_OK (individual non-finite energies show as status 3), or an
@@ -331,7 +334,7 @@ typedef struct {
   int32_t vkind;           /* 0: v = 1; 1: v = (1 - |k|/K)^2, computed by the library   */
   const double* pos_host;  /* double[2][d][N] fractional starting positions (host), or NULL */
   uint64_t seed;           /* the start's seed when pos_host is NULL                   */
-  ss_min_opts opts;        /* minimiser options (L-BFGS: method 0; any precision)      */
+  ss_min_opts opts;        /* minimiser options (L-BFGS or FIRE; any precision)        */
 } ss_request;
 
 /* Independent uniform fractional positions in [0, 1)^d (the paper's Poisson

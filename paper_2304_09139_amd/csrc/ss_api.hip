@@ -330,37 +330,52 @@ int64_t rounds_fit(int64_t capacity, int64_t per, int64_t max_steps, int rounds)
   return best;
 }
 
-// n(k) pass schedule for N particles: piece block b gets P_b particle ranges
-// whose work (longest piece + base cost) x (particles) is about equal across all
-// units, about two rounds of resident blocks in total; wavevectors of block b then
-// have P_b partial rows.  Depends only on (d, R2, N) and the device.
+// n(k) pass schedule for N particles: exactly kNkRounds rounds of resident
+// blocks in total (fewer only when N is small), apportioned over the piece blocks
+// in proportion to their work per particle (longest piece + base cost), so that
+// every unit costs about the same and the last round is as full as the first; the
+// P_b particle ranges of block b split [0, N) as evenly as integers allow (their
+// edges need not fall on the LDS tile of pt particles: a unit's last tile is
+// partial).  Wavevectors of block b then have P_b partial rows.  Depends only
+// on (d, R2, N) and the device.
 int nk_schedule(ss_ctx* ctx, Plan* pl, int64_t N, int pt, Plan::NkSched** out) {
   auto it = pl->nk_sched.find(N);
   if (it != pl->nk_sched.end()) {
     *out = &it->second;
     return SS_OK;
   }
-  // two rounds of resident blocks
-  const int64_t kTargetBlocks = 2 * (int64_t)num_cus(ctx) * nk_blocks_per_cu(pl->d, pt, pl->R + 1);
+  const int64_t target = (int64_t)kNkRounds * num_cus(ctx) * nk_blocks_per_cu(pl->d, pt, pl->R + 1);
   const size_t nb = pl->block_maxlen.size();
+  const int64_t maxP = std::max<int64_t>(1, (N + pt - 1) / pt);  // at least pt particles per unit
   double wsum = 0.0;
   for (int L : pl->block_maxlen) wsum += L + 1.5;
+  // largest-remainder apportionment of the target over the blocks
+  std::vector<int64_t> P(nb);
+  std::vector<std::pair<double, size_t>> rem;
+  int64_t given = 0;
+  for (size_t b = 0; b < nb; ++b) {
+    const double share = (double)target * (pl->block_maxlen[b] + 1.5) / wsum;
+    P[b] = std::max<int64_t>(1, std::min<int64_t>(maxP, (int64_t)share));
+    given += P[b];
+    rem.push_back({share - (double)(int64_t)share, b});
+  }
+  std::stable_sort(rem.begin(), rem.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  for (size_t q = 0; given < target && q < rem.size(); ++q)
+    if (P[rem[q].second] < maxP) {
+      P[rem[q].second] += 1;
+      ++given;
+    }
   std::vector<NkUnit> units;
   std::vector<int32_t> rows_of(pl->M, 1);
   int64_t maxrows = 1;
   for (size_t b = 0; b < nb; ++b) {
-    const double w = pl->block_maxlen[b] + 1.5;
-    int64_t Pb = (int64_t)std::llround((double)kTargetBlocks * w / wsum);
-    Pb = std::max<int64_t>(1, std::min<int64_t>(Pb, (N + pt - 1) / pt));
-    int64_t chunk = (N + Pb - 1) / Pb;
-    chunk = ((chunk + pt - 1) / pt) * pt;
-    Pb = (N + chunk - 1) / chunk;
+    const int64_t Pb = P[b];
     for (int64_t r = 0; r < Pb; ++r) {
       NkUnit u;
       u.block = (int32_t)b;
       u.row = (int32_t)r;
-      u.j0 = (int32_t)(r * chunk);
-      u.j1 = (int32_t)std::min<int64_t>(N, (r + 1) * chunk);
+      u.j0 = (int32_t)(r * N / Pb);
+      u.j1 = (int32_t)((r + 1) * N / Pb);
       units.push_back(u);
     }
     maxrows = std::max(maxrows, Pb);

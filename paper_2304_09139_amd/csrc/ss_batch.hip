@@ -52,14 +52,12 @@ int setup_slot(ss_ctx* ctx, const ss_problem* p, const ss_min_opts* op, HostSlot
     ctx->last_error = "invalid minimiser options";
     return SS_EINVAL;
   }
-  if (op->method != 0) {
-    ctx->last_error = "batched quenches run L-BFGS (method 0)";
-    return SS_EINVAL;
-  }
   h->prob = *p;
   h->opts = *op;
   h->nv = (int64_t)p->d * p->N;
-  h->m = op->history;
+  // FIRE keeps no (s, y) history: the smallest history layout holds its
+  // velocity products (3 of the 2 m + 2 product slots)
+  h->m = op->method == 1 ? 1 : op->history;
   h->G = dot_blocks_of(h->nv);
   h->bytes = al256(h->c.total) + min_bytes(h->nv, h->m, h->G);
   const int groups = (h->c.R1 + kTabRun - 1) / kTabRun;

@@ -110,6 +110,10 @@ constexpr int kXcds = 8;          // accelerator complex dies (one L2 each); wor
 constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)
 constexpr int64_t kDefaultGradK = 1024;
 constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks per n(k) piece block
+#ifndef SS_NK_ROUNDS
+#define SS_NK_ROUNDS 3
+#endif
+constexpr int kNkRounds = SS_NK_ROUNDS;     // rounds of resident blocks in a single-launch n(k) pass
 // d = 2 evaluations use the tiled n(k) pass (k_nk2) from R = kNk2MinR on; single
 // launches also from R = kNk2SmallR on when N <= kNk2SmallN, where the piece
 // walk's grid is small (measured: the walk is faster in between, e.g. N = 8000 at

@@ -633,11 +633,11 @@ __global__ void __launch_bounds__(kThreads) k_fire_dots(VecSet V, const MinState
 }
 
 // one block: the three products in range order, then the FIRE decisions
-__global__ void __launch_bounds__(kThreads) k_fire_final(MinState* S_, int G, const double* __restrict__ partial) {
+// (every thread of the block calls it; wave 0 works)
+__device__ __forceinline__ void fire_final_body(MinState* S_, int G, const double* __restrict__ partial) {
   MinState& S = *S_;
   if (!S.running) return;
   const int tid = threadIdx.x;
-  if (tid >= 64) return;
   __shared__ double s_d[kFireDots][2];
   if (tid < kFireDots) {
     dd r{0.0, 0.0};
@@ -674,11 +674,16 @@ __global__ void __launch_bounds__(kThreads) k_fire_final(MinState* S_, int G, co
   }
 }
 
-// v <- mix(v, g); v <- v - dt g; x <- x + dt v
-__global__ void __launch_bounds__(kThreads) k_fire_step(VecSet V, const MinState* S_, int64_t nv) {
+__global__ void __launch_bounds__(64) k_fire_final(MinState* S_, int G, const double* __restrict__ partial) {
+  fire_final_body(S_, G, partial);
+}
+
+// v <- mix(v, g); v <- v - dt g; x_new <- x + dt v, written to x (single
+// quenches evaluate in place) or to xt (batched quenches, accepted afterwards)
+__device__ __forceinline__ void fire_step_body(const VecSet& V, const MinState* S_, int64_t nv, int64_t i,
+                                               double* __restrict__ xnew) {
   const MinState& S = *S_;
   if (!S.running) return;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= nv) return;
   const double dt = S.fdt;
   const dd g = vload(V.g, nv, i);
@@ -690,14 +695,20 @@ __global__ void __launch_bounds__(kThreads) k_fire_step(VecSet V, const MinState
   if (i == 0 && S.fault_iter > 0 && S.iter + 1 == S.fault_iter) x.h = __builtin_nan("");
   V.p[i] = v.h;
   V.p[nv + i] = v.l;
-  V.x[i] = x.h;
-  V.x[nv + i] = x.l;
+  xnew[i] = x.h;
+  xnew[nv + i] = x.l;
+}
+
+__global__ void __launch_bounds__(kThreads) k_fire_step(VecSet V, const MinState* S_, int64_t nv) {
+  fire_step_body(V, S_, nv, (int64_t)blockIdx.x * kThreads + threadIdx.x, V.x);
 }
 
 // after the evaluation at the new x: Phi and S_max from the energy pass's block
-// partials, the finite check and the start-of-iteration tests
-__global__ void __launch_bounds__(kThreads) k_fire_top(MinState* S_, MinParams P, const double* __restrict__ eblk,
-                                                       int64_t neblk) {
+// partials, the finite check and the start-of-iteration tests (every thread of
+// a kThreads block calls it); accept != 0 marks the step for the batched
+// acceptance copy x <- xt, g <- gt
+__device__ __forceinline__ void fire_top_body(MinState* S_, const MinParams& P, const double* __restrict__ eblk,
+                                              int64_t neblk, int accept) {
   MinState& S = *S_;
   if (!S.running) return;
   dd phi, sm;
@@ -711,6 +722,7 @@ __global__ void __launch_bounds__(kThreads) k_fire_top(MinState* S_, MinParams P
     S.evals += 1;
     st(S.f, phi);
     st(S.smax, sm);
+    S.accepted = accept;
   }
   if (!isfinite(phi.h)) {
     if (tid == 0) {
@@ -720,6 +732,11 @@ __global__ void __launch_bounds__(kThreads) k_fire_top(MinState* S_, MinParams P
     return;
   }
   top_of_iteration(S, P, tid, it, phi, sm);
+}
+
+__global__ void __launch_bounds__(kThreads) k_fire_top(MinState* S_, MinParams P, const double* __restrict__ eblk,
+                                                       int64_t neblk) {
+  fire_top_body(S_, P, eblk, neblk, 0);
 }
 
 // FIRE start: dt0 from the host, v = 0, a = 0.1
@@ -805,23 +822,42 @@ __global__ void __launch_bounds__(kThreads) k_accept(VecSet V, const MinState* S
 // batched minimiser kernels: the same bodies over many configurations (see the
 // batched energy kernels for the unit convention)
 // ---------------------------------------------------------------------------
+// A FIRE configuration (P.method 1) maps its step onto the same launches: the
+// direction products compute g.v, g.g, v.v (the first 3 of the G (2m + 2)
+// units), the direction block takes the FIRE decisions, the step writes the new
+// positions to xt, the trial evaluation is the step's evaluation, the decision
+// block runs the stopping tests and always accepts, and the acceptance copies
+// xt, gt to x, g -- the same arithmetic as a single FIRE quench.
 __global__ void __launch_bounds__(kThreads) kb_dots(const MinSlot* __restrict__ ms, const BUnit* __restrict__ units,
                                                     int mode) {
   const BUnit u = units[blockIdx.x];
   const MinSlot& C = ms[u.slot];
   const int G = C.dot_blocks;
+  if (C.P.method == 1) {
+    if (mode == 0 && u.idx / G < kFireDots) fire_dots_body(C.V, C.S, C.nv, C.partial, u.idx % G, u.idx / G, G);
+    return;
+  }
   dots_body(C.V, C.S, mode, C.nv, C.partial, u.idx % G, u.idx / G, G);
 }
 
 __global__ void __launch_bounds__(kThreads) kb_dots_final(const MinSlot* __restrict__ ms,
                                                           const int32_t* __restrict__ list, int mode) {
   const MinSlot& C = ms[list[blockIdx.x]];
+  if (C.P.method == 1) {
+    if (mode == 0) fire_final_body(C.S, C.dot_blocks, C.partial);
+    else fire_top_body(C.S, C.P, C.eblk, C.neblk, 1);
+    return;
+  }
   dots_final_body(C.S, C.P, mode, C.dot_blocks, C.partial, C.eblk, C.neblk);
 }
 
 __global__ void __launch_bounds__(kThreads) kb_step(const MinSlot* __restrict__ ms, const BUnit* __restrict__ units) {
   const BUnit u = units[blockIdx.x];
   const MinSlot& C = ms[u.slot];
+  if (C.P.method == 1) {
+    fire_step_body(C.V, C.S, C.nv, (int64_t)u.idx * kThreads + threadIdx.x, C.V.xt);
+    return;
+  }
   step_body(C.V, C.S, C.nv, u.idx);
 }
 
@@ -832,9 +868,42 @@ __global__ void __launch_bounds__(kThreads) kb_accept(const MinSlot* __restrict_
   accept_body(C.V, C.S, C.nv, u.idx);
 }
 
+// FIRE start of a batched configuration (one 64-thread block): v = 0, a = 0.1
+// and dt0 = sqrt(step / max|g(x0)|) (dt_max = 10 dt0), the same IEEE
+// operations the single quench does on the host
+__device__ __forceinline__ void fire_init_block(const MinSlot& C) {
+  const int tid = threadIdx.x;
+  __shared__ double s_h[64], s_l[64];
+  dd m{0.0, 0.0};
+  for (int64_t i = tid; i < C.nv; i += 64) {
+    C.V.p[i] = 0.0;
+    C.V.p[C.nv + i] = 0.0;
+    dd x = vload(C.V.g, C.nv, i);
+    if (x.h < 0.0) x = dd_neg(x);
+    if (dd_less(m, x)) m = x;
+  }
+  s_h[tid] = m.h;
+  s_l[tid] = m.l;
+  __syncthreads();
+  if (tid != 0) return;
+  for (int w = 1; w < 64; ++w)
+    if (dd_less(m, dd{s_h[w], s_l[w]})) m = dd{s_h[w], s_l[w]};
+  MinState& S = *C.S;
+  const double dt0 = m.h > 0.0 ? sqrt(C.P.step / m.h) : 0.0;
+  S.fdt = dt0;
+  S.fdt_max = 10.0 * dt0;
+  S.fa = 0.1;
+  S.npos = 0;
+  S.fire_reset = 0;
+}
+
 __global__ void __launch_bounds__(64) kb_init(const MinSlot* __restrict__ ms, const int32_t* __restrict__ list) {
   const MinSlot& C = ms[list[blockIdx.x]];
   init_body(C.S, C.P, C.keep);
+  if (C.P.method == 1) {
+    __syncthreads();
+    fire_init_block(C);
+  }
 }
 
 // status of each listed configuration, gathered for one copy to the host
@@ -937,6 +1006,7 @@ MinParams min_params(const ss_min_opts* op, const ss_problem* prob) {
   P.c1 = op->c1;
   P.step = op->step_cap * pow((double)prob->N, -1.0 / (double)prob->d);
   P.fault_iter = op->fault_iter;
+  P.method = op->method;
   return P;
 }
 

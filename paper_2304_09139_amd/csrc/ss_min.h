@@ -46,6 +46,7 @@ struct MinParams {
   int64_t max_iter;
   double s_floor, stall_ratio, c1, step;  // step = step_cap * N^(-1/d)
   int64_t fault_iter;                     // failure injection (ss_min_opts), 0 = off
+  int32_t method;                         // 0 L-BFGS, 1 FIRE
 };
 
 // the vectors of one quench

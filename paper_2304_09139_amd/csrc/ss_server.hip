@@ -511,8 +511,8 @@ int check_request(ss_ctx* ctx, const ss_request* q, ss_problem* p) {
     ctx->last_error = "served requests take vkind 0 or 1";
     return SS_EINVAL;
   }
-  if (!min_opts_valid(&q->opts) || q->opts.method != 0) {
-    ctx->last_error = "invalid minimiser options (served quenches use L-BFGS, method 0)";
+  if (!min_opts_valid(&q->opts)) {
+    ctx->last_error = "invalid minimiser options";
     return SS_EINVAL;
   }
   if (!(q->L > 0.0) || !isfinite(q->L)) {

@@ -154,3 +154,28 @@ def test_tiles_and_errors(ctx):
     r = ctx.minimize_batch([w], [x], opts=dict(max_iter=0))[0]
     assert r["iters"] == 0 and r["status"] == "max_iter"
     assert np.array_equal(x.cpu().numpy(), pos)
+
+
+def test_numeric_fault_isolated_in_batch(ctx):
+    """One configuration of a batch whose energy turns non-finite (a NaN injected
+    into its trial point of iteration 5) stops with status 3 (numeric); every
+    other configuration gives the same bits as alone."""
+    items = [setup(ctx, s) for s in MIX]
+    opts = dict(max_iter=30, s_floor=0.0)
+    alone = []
+    for w, n, v, pos in items:
+        x = dev(pos)
+        r = ctx.minimize_batch([w], [x], [v], opts=opts)[0]
+        alone.append((x.cpu().numpy(), r))
+    bad = 3
+    xs = [dev(it[3]) for it in items]
+    olist = [dict(opts, fault_iter=5 if i == bad else 0) for i in range(len(items))]
+    res = ctx.minimize_batch([it[0] for it in items], xs, [it[2] for it in items], opts=olist)
+    for i, (x, r) in enumerate(zip(xs, res)):
+        if i == bad:
+            assert r["status"] == "numeric", r
+            assert r["iters"] == 5, r  # the faulted iteration counts
+            continue
+        xa, ra = alone[i]
+        assert np.array_equal(x.cpu().numpy(), xa), MIX[i]
+        assert r["phi"] == ra["phi"] and r["iters"] == ra["iters"] and r["status"] == ra["status"], MIX[i]

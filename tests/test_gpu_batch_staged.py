@@ -114,7 +114,7 @@ def test_mixed_precision_batch_alone_vs_mix_bitwise(ctx):
 
 def test_batch_precision_option_errors(ctx):
     w, n, v, pos = setup(ctx, SPECS[0])
-    for bad in (dict(precision=3), dict(precision=2, fp64_floor=-1.0), dict(method=1)):
+    for bad in (dict(precision=3), dict(precision=2, fp64_floor=-1.0), dict(method=2)):
         with pytest.raises(ss.SSError) as e:
             ctx.minimize_batch([w], [dev(pos)], opts=bad)
         assert e.value.code == ss.SS_EINVAL

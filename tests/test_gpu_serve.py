@@ -154,14 +154,16 @@ def test_small_arena_admission(ctx):
     ctx.server_start(int(need * 1.5), max_slots=4)
     try:
         big = ss.Workload.from_chi(3, 6000, 0.45)
-        tb = ctx.submit(big, inputs.config_positions(46, 3, 6000, 0), max_iter=5)
+        # larger than the whole arena: refused at submission, nothing queued
+        with pytest.raises(ss.SSError) as e:
+            ctx.submit(big, inputs.config_positions(46, 3, 6000, 0), max_iter=5)
+        assert e.value.code == ss.SS_ENOMEM
         tickets = [ctx.submit(w, pos, max_iter=40, s_floor=0.0) for w, pos in items]
         for t in tickets:
             r, _ = wait(ctx, t)
             assert r["iters"] == 40
-        with pytest.raises(ss.SSError) as e:
-            wait(ctx, tb)
-        assert e.value.code == ss.SS_ENOMEM
+        st = ctx.server_stats()
+        assert st["submitted"] == 3 and st["completed"] == 3, st
     finally:
         ctx.server_stop()
 
@@ -176,7 +178,7 @@ def test_serving_errors(ctx):
         with pytest.raises(ss.SSError) as e:
             ctx.server_start(1 << 20, max_slots=2)
         assert e.value.code == ss.SS_ESTATE
-        for bad in (dict(history=0), dict(method=1), dict(precision=3)):
+        for bad in (dict(history=0), dict(method=2), dict(precision=3)):
             with pytest.raises(ss.SSError) as e:
                 ctx.submit(w, pos, **bad)
             assert e.value.code == ss.SS_EINVAL
@@ -193,3 +195,73 @@ def test_serving_errors(ctx):
     finally:
         ctx.server_stop()
     ctx.server_stop()  # stopping twice is harmless
+
+
+def test_requests_overlap_and_stay_bitwise(ctx):
+    """Continuous batching: requests submitted while others run are admitted at
+    step boundaries and run together (the server's peak count of running
+    configurations is at least 2 and it admitted requests while others were
+    running), and each result is still the batch of one's bit for bit."""
+    items = [make(s) for s in SPECS]
+    opts = dict(max_iter=200, s_floor=0.0)
+    ref = []
+    for w, pos in items:
+        x = torch.from_numpy(pos).cuda()
+        v = ctx.weights(w, ctx.wavevectors(w.d, w.R2)) if w.vkind else None
+        r = ctx.minimize_batch([w], [x], [v], opts=opts)[0]
+        ref.append((r, x.cpu().numpy()))
+    ctx.server_start(1 << 30, max_slots=8)
+    try:
+        first = ctx.submit(items[3][0], items[3][1], **opts)
+        # wait until the first request is running, then submit the others
+        t0 = time.time()
+        while ctx.server_stats()["running"] < 1 and ctx.poll(first) is None:
+            assert time.time() - t0 < 60
+            time.sleep(0.0005)
+        tickets = {3: first}
+        for i in [0, 4, 1, 2]:
+            tickets[i] = ctx.submit(items[i][0], items[i][1], **opts)
+        results = {i: wait(ctx, t) for i, t in tickets.items()}
+        st = ctx.server_stats()
+        print("server counters:", st)
+        assert st["max_running"] >= 2, st
+        assert st["admitted"] == 5 and st["completed"] == 5, st
+        for i, (r, xs) in results.items():
+            rb, xb = ref[i]
+            assert np.array_equal(xs, xb), SPECS[i]
+            assert r["phi"] == rb["phi"] and r["iters"] == rb["iters"] == 200, SPECS[i]
+    finally:
+        ctx.server_stop()
+
+
+def test_numeric_fault_isolated_in_server(ctx):
+    """A request whose energy turns non-finite (a NaN injected into its trial
+    point of iteration 7) ends on its own with status 3 (numeric); the requests
+    served beside it give the same bits as the batch of one."""
+    items = [make(s) for s in SPECS[:4]]
+    opts = dict(max_iter=40, s_floor=0.0)
+    ref = []
+    for w, pos in items:
+        x = torch.from_numpy(pos).cuda()
+        v = ctx.weights(w, ctx.wavevectors(w.d, w.R2)) if w.vkind else None
+        r = ctx.minimize_batch([w], [x], [v], opts=opts)[0]
+        ref.append((r, x.cpu().numpy()))
+    bad = 1
+    ctx.server_start(1 << 30, max_slots=8)
+    try:
+        tickets = {i: ctx.submit(w, pos, **dict(opts, fault_iter=7 if i == bad else 0))
+                   for i, (w, pos) in enumerate(items)}
+        for i, t in tickets.items():
+            r, xs = wait(ctx, t)
+            if i == bad:
+                assert r["status"] == "numeric", r
+                assert r["iters"] == 7, r  # the faulted iteration counts
+                continue
+            rb, xb = ref[i]
+            assert np.array_equal(xs, xb), SPECS[i]
+            assert r["phi"] == rb["phi"] and r["iters"] == rb["iters"] == 40, SPECS[i]
+        # the server keeps serving after the fault
+        r, xs = wait(ctx, ctx.submit(items[0][0], items[0][1], **opts))
+        assert np.array_equal(xs, ref[0][1])
+    finally:
+        ctx.server_stop()
