@@ -142,6 +142,26 @@ int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, co
                    const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * evaluation of ss_energy_grad with the same arguments, layouts, kernels and
+ * results bit for bit, minus the workspace -- it runs in the library's own
+ * static device array of ss_static_scratch_bytes() bytes (32 MiB; one per GPU,
+ * held until the process ends).  It calls no hipMalloc, hipFree or other
+ * allocating routine.  The problem must have been prepared beforehand by
+ * ss_workspace_size(op = 0) on the same context (that call builds and caches
+ * the wavevector plan, schedules and chunk bounds); otherwise SS_ESTATE.
+ * SS_ENOMEM (nothing launched) when the problem's workspace,
+ * ss_workspace_size(op = 0), exceeds the scratch size.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (two streams, two
+ * contexts or two threads at once) race and give wrong results: serialise
+ * them.  Async, like ss_energy_grad; nothing in the array needs clearing
+ * between calls (every value read is written earlier in the same call). */
+int ss_energy_grad_static(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
+                          const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
+                          void* stream);
+size_t ss_static_scratch_bytes(void);
+
 /* The same evaluation with the two pair passes in plain FP64 (the first stage
  * of a staged quench; see ss_min_opts.precision).  Same arguments, layouts and
  * errors as ss_energy_grad; every output low word is zero.  Each term of a

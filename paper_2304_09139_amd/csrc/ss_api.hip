@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -53,6 +55,46 @@ hipError_t launch_nk2_64(const int32_t* tiles, int64_t ntiles, const int32_t* le
 using namespace ss;
 
 namespace {
+
+// Set while the allocation-free entry point runs on this thread: the plan,
+// schedule and chunk-bound builders, which allocate device memory on first use,
+// refuse instead (the problem must have been prepared by ss_workspace_size).
+thread_local bool tl_no_alloc = false;
+
+struct NoAllocScope {
+  NoAllocScope() { tl_no_alloc = true; }
+  ~NoAllocScope() { tl_no_alloc = false; }
+};
+
+// Workspace of ss_energy_grad_static: one static device array per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a kernel
+// (in host code the name is a host-side stand-in, not a device address); it
+// uses the device address hipGetSymbolAddress gives for each device, looked up
+// once per device at ss_create.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of that device's `scratch`
+
+// the current device's `scratch` address (the device must be current)
+int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SS_EHIP;
+    it = g_scratch_addr.emplace(device, p).first;
+  }
+  *out = it->second;
+  return SS_OK;
+}
+
+int refuse_alloc(ss_ctx* c, const char* what) {
+  c->last_error = std::string(what) + " of this problem has not been built: call ss_workspace_size for it "
+                  "before ss_energy_grad_static";
+  return SS_ESTATE;
+}
 
 int set_err(ss_ctx* c, int code, const std::string& msg) {
   if (c) c->last_error = msg;
@@ -144,6 +186,7 @@ int build_plan(ss_ctx* ctx, int d, int64_t R2, Plan** out) {
     *out = it->second;
     return SS_OK;
   }
+  if (tl_no_alloc) return refuse_alloc(ctx, "the wavevector plan");
   Plan* pl = new (std::nothrow) Plan();
   if (!pl) return set_err(ctx, SS_ENOMEM, "plan allocation");
   pl->d = d;
@@ -281,6 +324,7 @@ int chunk_bounds(ss_ctx* ctx, Plan* pl, int Q, int32_t** out) {
     *out = it->second;
     return SS_OK;
   }
+  if (tl_no_alloc) return refuse_alloc(ctx, "the gradient chunk bounds");
   std::vector<int32_t> b(Q + 1);
   const int64_t total = pl->run_len_prefix.back();
   size_t r = 0;
@@ -344,6 +388,7 @@ int nk_schedule(ss_ctx* ctx, Plan* pl, int64_t N, int pt, Plan::NkSched** out) {
     *out = &it->second;
     return SS_OK;
   }
+  if (tl_no_alloc) return refuse_alloc(ctx, "the n(k) schedule");
   const int64_t target = (int64_t)kNkRounds * num_cus(ctx) * nk_blocks_per_cu(pl->d, pt, pl->R + 1);
   const size_t nb = pl->block_maxlen.size();
   const int64_t maxP = std::max<int64_t>(1, (N + pt - 1) / pt);  // at least pt particles per unit
@@ -435,6 +480,7 @@ int nk2_schedule(ss_ctx* ctx, Plan* pl, int64_t N, Plan::Nk2Sched** out) {
     *out = &it->second;
     return SS_OK;
   }
+  if (tl_no_alloc) return refuse_alloc(ctx, "the tiled n(k) schedule");
   const int64_t target = 2 * (int64_t)num_cus(ctx) * nk2_blocks_per_cu();
   int64_t nrows = std::max<int64_t>(1, (target + pl->t2_ntiles / 2) / std::max<int64_t>(1, pl->t2_ntiles));
   nrows = std::min<int64_t>(nrows, std::min<int64_t>(kMaxNkRows, (N + 15) / 16));
@@ -696,6 +742,10 @@ int ss_create(int device, ss_ctx** out) {
   ss_ctx* c = new (std::nothrow) ss_ctx();
   if (!c) return SS_ENOMEM;
   c->device = device;
+  if (scratch_address(device, &c->scratch) != SS_OK) {
+    delete c;
+    return SS_EHIP;
+  }
   if (hipStreamCreateWithFlags(&c->build_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return SS_EHIP;
@@ -829,6 +879,14 @@ int ss_workspace_size(ss_ctx* ctx, const ss_problem* prob, int op, size_t* bytes
   LaunchCfg c;
   int rc = prepare(ctx, prob, &pl, &c);
   if (rc) return rc;
+  // the gradient chunk bounds too, so that everything a later
+  // ss_energy_grad_static call needs exists
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    int32_t* cb = nullptr;
+    rc = chunk_bounds(ctx, pl, c.Q * kWaves, &cb);
+    if (rc) return rc;
+  }
   *bytes = c.total + (op == 1 ? minimize_extra_bytes((int64_t)prob->d * prob->N) : 0);
   return SS_OK;
 }
@@ -892,6 +950,27 @@ int ss_energy_grad(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, co
   return energy_grad_entry(ctx, prob, n_dev, v_dev, pos_dev, phi_dev, smax_dev, grad_dev, nk_dev, ws, ws_bytes,
                            stream, 0);
 }
+
+int ss_energy_grad_static(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
+                          const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,
+                          void* stream) {
+  if (!ctx) return SS_EINVAL;
+  NoAllocScope no_alloc;
+  Plan* pl = nullptr;
+  LaunchCfg c;
+  int rc = prepare(ctx, prob, &pl, &c);
+  if (rc) return rc;
+  if (!n_dev || !pos_dev || !phi_dev) return set_err(ctx, SS_EINVAL, "NULL required pointer");
+  if (prob->vkind != 0 && !v_dev) return set_err(ctx, SS_EINVAL, "vkind != 0 needs v_dev");
+  if (c.total > kScratchBytes)
+    return set_err(ctx, SS_ENOMEM, "the problem needs " + std::to_string(c.total) +
+                                       " workspace bytes, the static scratch holds " + std::to_string(kScratchBytes));
+  if (!ctx->scratch) return set_err(ctx, SS_EHIP, "no static scratch address for this device");
+  return energy_grad_impl(ctx, prob, pl, c, v_dev, pos_dev, phi_dev, smax_dev, grad_dev, nk_dev, (char*)ctx->scratch,
+                          (hipStream_t)stream, nullptr, nullptr, false);
+}
+
+size_t ss_static_scratch_bytes(void) { return kScratchBytes; }
 
 int ss_energy_grad_fp64(ss_ctx* ctx, const ss_problem* prob, const int32_t* n_dev, const double* v_dev,
                         const double* pos_dev, double* phi_dev, double* smax_dev, double* grad_dev, double* nk_dev,

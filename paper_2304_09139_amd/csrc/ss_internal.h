@@ -174,4 +174,5 @@ struct ss_ctx {
   std::map<std::pair<int, int64_t>, ss::Plan*> plans;
   hipStream_t build_stream = nullptr;
   ss::ProfileLog prof;
+  void* scratch = nullptr;  // this device's static scratch (ss_energy_grad_static)
 };

@@ -83,6 +83,8 @@ SIGNATURES = {
                                       ctypes.c_size_t, _V]),
     "ss_energy_grad_fp64": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V, _V, _V, _V, _V, _V,
                                            ctypes.c_size_t, _V]),
+    "ss_energy_grad_static": (ctypes.c_int, [_V, ctypes.POINTER(Problem), _V, _V, _V, _V, _V, _V, _V, _V]),
+    "ss_static_scratch_bytes": (ctypes.c_size_t, []),
     "ss_set_progress": (ctypes.c_int, [_V, ctypes.c_double]),
     "ss_profile_enable": (ctypes.c_int, [_V, ctypes.c_int]),
     "ss_profile_read": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int, _I64P, ctypes.POINTER(ctypes.c_double),
@@ -354,6 +356,25 @@ class Context:
                      _ptr(o.get("nk") if nk else None), _ptr(ws), ws.numel(),
                      _stream(dev)), "ss_energy_grad")
         return o
+
+    def energy_grad_static(self, w: Workload, n: torch.Tensor, v: torch.Tensor | None, pos: torch.Tensor,
+                           out: dict, grad: bool = True, nk: bool = False) -> dict:
+        """ss_energy_grad_static: the evaluation of energy_grad in the library's
+        static scratch (no allocation by the library).  The caller passes the
+        outputs in `out` ("phi", "smax"[, "grad"][, "nk"], device float64) and
+        has prepared the problem with workspace_size(w)."""
+        dev = self.device
+        _need_problem(self, w, n, v, pos)
+        for k, shape in (("phi", (2,)), ("smax", (2,)), ("grad", (2, w.d, w.N)), ("nk", (4, w.M))):
+            if k in ("phi", "smax") or (k == "grad" and grad) or (k == "nk" and nk):
+                _need(out.get(k), dev, torch.float64, shape, f"output {k}")
+        p = w.problem()
+        self._chk(lib().ss_energy_grad_static(self._h, ctypes.byref(p), _ptr(n), _ptr(v), _ptr(pos),
+                                              _ptr(out["phi"]), _ptr(out["smax"]),
+                                              _ptr(out["grad"]) if grad else None,
+                                              _ptr(out["nk"]) if nk else None, _stream(dev)),
+                  "ss_energy_grad_static")
+        return out
 
     def minimize(self, w: Workload, n: torch.Tensor, v: torch.Tensor | None, pos: torch.Tensor,
                  **opts) -> dict:
