@@ -62,8 +62,9 @@ WORKLOADS = {
     # 200 requests served with continuous batching: d in {2, 3}, N log-uniform in
     # [500, 5000], chi uniform in [0.1, 0.49], Poisson arrivals at 0.7 x capacity
     "serve200_d2-3_N500-5000": dict(serve=200, stream_seed=5, cfg_id=6),
-    # the same stream shape at N log-uniform in [1e3, 1e5] (24 requests: the large
-    # ones take seconds each)
+    # the same stream shape at N log-uniform in [1e3, 1e5] (the large requests take
+    # seconds each)
+    "serve200_d2-3_N1e3-1e5": dict(serve=200, stream_seed=8, cfg_id=7, n_min=1000, n_max=100000, arena_gb=96),
     "serve24_d2-3_N1e3-1e5": dict(serve=24, stream_seed=8, cfg_id=7, n_min=1000, n_max=100000, arena_gb=96),
     # the paper's production shape, one Phi + gradient evaluation at a time (a
     # quench at this size takes hours): d = 2, N = 2e6, chi = 0.1 and 0.4
@@ -254,6 +255,7 @@ def main():
                     help="report the 256-bit error of n~ at sampled k of the final configuration")
     ap.add_argument("--method", default="lbfgs", choices=("lbfgs", "fire"),
                     help="minimiser of the single-configuration quench")
+    ap.add_argument("--history", type=int, default=8, help="L-BFGS history length of single-configuration quenches")
     ap.add_argument("--precision", default="dd", choices=("dd", "staged", "fp64"),
                     help="evaluation precision of the quench (staged: FP64 until it stalls, then dd)")
     ap.add_argument("--evals", type=int, default=0,
@@ -292,7 +294,7 @@ def main():
     w = ss.Workload.from_chi(d, N, chi, vkind=vkind)
     n = ctx.wavevectors(d, w.R2)
     v = ctx.weights(w, n) if vkind else None
-    mopts = dict(s_floor=FLOOR, precision=args.precision, method=args.method)
+    mopts = dict(s_floor=FLOOR, precision=args.precision, method=args.method, history=args.history)
     if args.method == "fire":
         mopts["stall_window"] = 200
     # all starting configurations resident in HBM before the timed region
@@ -411,7 +413,8 @@ def main():
                                + ("v(k)=(1-|k|/K)^2" if vkind else "v(k)=1")
                                + ("" if args.precision == "dd" else f", {args.precision} precision"),
                    "d": d, "N": N, "chi": chi, "R2": w.R2, "M": w.M, "s_floor": FLOOR, "vkind": vkind,
-                   "precision": args.precision, "method": args.method, "parallelism": "single GPU"},
+                   "precision": args.precision, "method": args.method, "history": args.history,
+                   "parallelism": "single GPU"},
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{args.steps}",
         "staged_precision": staged if staged is None else dict(
@@ -793,12 +796,18 @@ def bench_serve(args, wl):
     arena = wl.get("arena_gb", 8) << 30
     ctx.server_start(arena, max_slots=512)
 
+    trace = []
+
     def run(times):
-        """Submit request i at times[i] (seconds from the start), collect all."""
+        """Submit request i at times[i] (seconds from the start), collect all;
+        the server's running and queued counts are sampled every 0.25 s."""
+        trace.clear()
         t0 = time.perf_counter()
+        t_sample = -1.0
         tickets = []
         done = {}
         i = 0
+        last = 0.0
         while len(done) < count:
             now = time.perf_counter() - t0
             while i < count and times[i] <= now:
@@ -809,9 +818,13 @@ def bench_serve(args, wl):
                     r = ctx.poll(t)
                     if r is not None:
                         done[k] = r[0]
-                        if count <= 50:  # long requests: a line per completion
-                            print(f"[serve] {len(done)}/{count} done, t {time.perf_counter() - t0:.1f}s",
-                                  file=sys.stderr, flush=True)
+            if time.perf_counter() - t0 - t_sample >= 0.25:
+                t_sample = time.perf_counter() - t0
+                st = ctx.server_stats()
+                trace.append((t_sample, st["running"], st["queued"]))
+            if time.perf_counter() - t0 - last >= 10.0:  # a progress line every 10 s
+                last = time.perf_counter() - t0
+                print(f"[serve] {len(done)}/{count} done, {i} submitted, t {last:.1f}s", file=sys.stderr, flush=True)
             time.sleep(0.0005)
         return time.perf_counter() - t0, [done[k] for k in range(count)]
 
@@ -822,8 +835,17 @@ def bench_serve(args, wl):
             time.sleep(0.001)
     closed_s, closed = run([0.0] * count)
     cap = sum(1 for r in closed if r["status"] == "converged") / closed_s
+
+    def occupancy(tr):
+        run_counts = np.array([r for _, r, _ in tr]) if tr else np.zeros(1)
+        return {"mean_running": float(run_counts.mean()), "frac_time_one_running": float((run_counts <= 1).mean()),
+                "max_running": int(run_counts.max())}
+    closed_occ = occupancy(trace)
+    stats_closed = ctx.server_stats()
     lam = 0.7 * cap
     open_s, opened = run([t / lam for *_, t in stream])
+    open_occ = occupancy(trace)
+    stats_all = ctx.server_stats()
     ctx.server_stop()
     seq_conv, seq_s = 0, float("nan")
     if not args.no_sequential:
@@ -834,9 +856,13 @@ def bench_serve(args, wl):
         ns = [ctx.wavevectors(w.d, w.R2) for w in works]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for w, n, x in zip(works, ns, xs):
+        last = 0.0
+        for q, (w, n, x) in enumerate(zip(works, ns, xs)):
             r = ctx.minimize(w, n, None, x, s_floor=FLOOR)  # the plain path: double-double
             seq_conv += r["status"] == "converged"
+            if time.perf_counter() - t1 - last >= 10.0:
+                last = time.perf_counter() - t1
+                print(f"[serve] one at a time: {q + 1}/{count} done, t {last:.1f}s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         seq_s = time.perf_counter() - t1
     lat = np.array([r["seconds"] for r in opened])
@@ -872,6 +898,13 @@ def bench_serve(args, wl):
         "closed_batch_latency_s": {"p50": float(np.percentile([r["seconds"] for r in closed], 50)),
                                    "p99": float(np.percentile([r["seconds"] for r in closed], 99))},
         "tiles": "tuned table" if load_tiles() else "built-in",
+        # where the time goes: the share of the double-double pair work in the
+        # requests with N >= 2e4, and the server's occupancy (sampled counts)
+        "pair_work_share_N_ge_2e4": sum(w.M * w.N * r["evals"] for w, r in zip(works, closed) if w.N >= 20000)
+        / max(1, sum(w.M * w.N * r["evals"] for w, r in zip(works, closed))),
+        "occupancy_closed": closed_occ,
+        "occupancy_poisson": open_occ,
+        "server_counters": {"closed": stats_closed, "total": stats_all},
     }
     print(json.dumps(out), flush=True)
     ctx.close()
