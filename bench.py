@@ -74,8 +74,10 @@ WORKLOADS = {
 
 
 def kernel_source_hash() -> str:
+    """Hash of the pair kernels and of the host code that shapes their launches
+    (schedules, tiles): counter summaries taken on other sources are ignored."""
     h = hashlib.sha256()
-    for f in ("ss_dd.h", "ss_kernels.hip"):
+    for f in ("ss_dd.h", "ss_kernels.hip", "ss_api.hip", "ss_internal.h"):
         with open(os.path.join(ROOT, "paper_2304_09139_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -255,6 +257,11 @@ def main():
                     help="report the 256-bit error of n~ at sampled k of the final configuration")
     ap.add_argument("--method", default="lbfgs", choices=("lbfgs", "fire"),
                     help="minimiser of the single-configuration quench")
+    ap.add_argument("--serve-phase", default="all", choices=("all", "closed", "open", "sequential"),
+                    help="served workloads: run every phase (default) or one: the closed run (all requests at "
+                         "once: capacity), the Poisson run at 0.7 x --serve-capacity, or the one-at-a-time path")
+    ap.add_argument("--serve-capacity", type=float, default=None,
+                    help="configs/s of a closed run, for --serve-phase open")
     ap.add_argument("--history", type=int, default=8, help="L-BFGS history length of single-configuration quenches")
     ap.add_argument("--precision", default="dd", choices=("dd", "staged", "fp64"),
                     help="evaluation precision of the quench (staged: FP64 until it stalls, then dd)")
@@ -813,6 +820,9 @@ def bench_serve(args, wl):
             while i < count and times[i] <= now:
                 tickets.append(ctx.submit(works[i], None, seed=seeds[i], s_floor=FLOOR, precision=args.precision))
                 i += 1
+                if i % 25 == 0 and times[i - 1] == 0.0:
+                    print(f"[serve] {i}/{count} submitted, t {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+                          flush=True)
             for k, t in enumerate(tickets):
                 if k not in done:
                     r = ctx.poll(t)
@@ -828,27 +838,50 @@ def bench_serve(args, wl):
             time.sleep(0.0005)
         return time.perf_counter() - t0, [done[k] for k in range(count)]
 
-    # warm-up: a few short requests (server buffers, first launches)
-    warm = [ctx.submit(works[i], None, seed=seeds[i], max_iter=2) for i in range(min(count, 8))]
+    # warm-up: a few short requests of the smallest configurations (server
+    # buffers, first launches)
+    small = sorted(range(count), key=lambda i: works[i].M * works[i].N)[:8]
+    warm = [ctx.submit(works[i], None, seed=seeds[i], max_iter=2) for i in small]
     for t in warm:
         while ctx.poll(t) is None:
             time.sleep(0.001)
-    closed_s, closed = run([0.0] * count)
-    cap = sum(1 for r in closed if r["status"] == "converged") / closed_s
+    print(f"[serve] warm-up done; {count} requests, N {min(w.N for w in works)}..{max(w.N for w in works)}",
+          file=sys.stderr, flush=True)
 
     def occupancy(tr):
         run_counts = np.array([r for _, r, _ in tr]) if tr else np.zeros(1)
         return {"mean_running": float(run_counts.mean()), "frac_time_one_running": float((run_counts <= 1).mean()),
                 "max_running": int(run_counts.max())}
-    closed_occ = occupancy(trace)
-    stats_closed = ctx.server_stats()
-    lam = 0.7 * cap
-    open_s, opened = run([t / lam for *_, t in stream])
-    open_occ = occupancy(trace)
-    stats_all = ctx.server_stats()
+
+    def latency(res):
+        lat = np.array([r["seconds"] for r in res])
+        return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "max": float(lat.max())}
+
+    phase = args.serve_phase
+    out_extra = {}
+    closed, opened, cap, closed_s, open_s, lam = None, None, args.serve_capacity, None, None, None
+    if phase in ("all", "closed"):
+        closed_s, closed = run([0.0] * count)
+        print(f"[serve] closed run: {closed_s:.1f}s", file=sys.stderr, flush=True)
+        cap = sum(1 for r in closed if r["status"] == "converged") / closed_s
+        out_extra["occupancy_closed"] = occupancy(trace)
+        out_extra["server_counters_closed"] = ctx.server_stats()
+        out_extra["closed_batch_latency_s"] = latency(closed)
+        # where the time goes: the share of the pair work in the requests with N >= 2e4
+        out_extra["pair_work_share_N_ge_2e4"] = (
+            sum(w.M * w.N * r["evals"] for w, r in zip(works, closed) if w.N >= 20000)
+            / max(1, sum(w.M * w.N * r["evals"] for w, r in zip(works, closed))))
+    if phase in ("all", "open"):
+        if not cap:
+            raise SystemExit("--serve-phase open needs --serve-capacity (configs/s of the closed run)")
+        lam = 0.7 * cap
+        open_s, opened = run([t / lam for *_, t in stream])
+        out_extra["occupancy_poisson"] = occupancy(trace)
+        out_extra["latency_s"] = latency(opened)
+    out_extra["server_counters_total"] = ctx.server_stats()
     ctx.server_stop()
     seq_conv, seq_s = 0, float("nan")
-    if not args.no_sequential:
+    if phase in ("all", "sequential") and not args.no_sequential:
         # the same requests quenched one at a time with ss_minimize (same floor)
         import torch
 
@@ -865,47 +898,43 @@ def bench_serve(args, wl):
                 print(f"[serve] one at a time: {q + 1}/{count} done, t {last:.1f}s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         seq_s = time.perf_counter() - t1
-    lat = np.array([r["seconds"] for r in opened])
-    pairs = sum(w.M * w.N * (r["evals"] - r["evals_fp64"]) for w, r in zip(works, opened))
-    conv = sum(1 for r in opened if r["status"] == "converged")
+        out_extra["one_at_a_time"] = {"configs_per_s": seq_conv / seq_s, "seconds": seq_s,
+                                      "converged": f"{seq_conv}/{count}", "precision": "dd"}
+        if cap:
+            out_extra["capacity_vs_one_at_a_time"] = cap / (seq_conv / seq_s)
+    # the line's value: the Poisson run when there is one, else the closed run
+    res, el = (opened, open_s) if opened is not None else (closed, closed_s)
+    if res is None:
+        res, el = [], float("nan")
+    pairs = sum(w.M * w.N * (r["evals"] - r["evals_fp64"]) for w, r in zip(works, res))
+    conv = sum(1 for r in res if r["status"] == "converged")
     out = {
         "metric": "dd particle-wavevector pairs/s (Phi+grad) and configs/s at stated max S(k) floor",
-        "value": pairs / open_s,
+        "value": pairs / el if res else None,
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 1,
-        "ms_per_step": open_s * 1e3,
+        "ms_per_step": el * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"dd": "dd", "staged": "f64 then dd", "fp64": "f64"}[args.precision],
         "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
         "config": {"workload": f"{count} served L-BFGS quenches to S_max <= {FLOOR:g}, d in {{2,3}}, "
-                               f"N log-uniform in [{n_min}, {n_max}], chi uniform in [0.1, 0.49], Poisson "
-                               f"arrivals at 0.7 x capacity"
+                               f"N log-uniform in [{n_min}, {n_max}], chi uniform in [0.1, 0.49]"
+                               + (", Poisson arrivals at 0.7 x capacity" if opened is not None else
+                                  ", all submitted at once" if closed is not None else "")
                                + ("" if args.precision == "dd" else f", {args.precision} precision"),
-                   "requests": count, "s_floor": FLOOR, "precision": args.precision, "parallelism": "single GPU"},
-        "configs_per_s": conv / open_s,
-        "converged": f"{conv}/{count}",
+                   "requests": count, "s_floor": FLOOR, "precision": args.precision, "phase": phase,
+                   "parallelism": "single GPU"},
+        "configs_per_s": conv / el if res else None,
+        "converged": f"{conv}/{len(res)}",
         "capacity_configs_per_s": cap,
-        "one_at_a_time": None if args.no_sequential else {
-            "configs_per_s": seq_conv / seq_s, "seconds": seq_s, "converged": f"{seq_conv}/{count}", "precision": "dd"},
-        "capacity_vs_one_at_a_time": None if args.no_sequential else cap / (seq_conv / seq_s),
         "arrival_rate_per_s": lam,
-        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                      "max": float(lat.max())},
-        "closed_batch_latency_s": {"p50": float(np.percentile([r["seconds"] for r in closed], 50)),
-                                   "p99": float(np.percentile([r["seconds"] for r in closed], 99))},
         "tiles": "tuned table" if load_tiles() else "built-in",
-        # where the time goes: the share of the double-double pair work in the
-        # requests with N >= 2e4, and the server's occupancy (sampled counts)
-        "pair_work_share_N_ge_2e4": sum(w.M * w.N * r["evals"] for w, r in zip(works, closed) if w.N >= 20000)
-        / max(1, sum(w.M * w.N * r["evals"] for w, r in zip(works, closed))),
-        "occupancy_closed": closed_occ,
-        "occupancy_poisson": open_occ,
-        "server_counters": {"closed": stats_closed, "total": stats_all},
     }
+    out.update(out_extra)
     print(json.dumps(out), flush=True)
     ctx.close()
 
