@@ -263,6 +263,8 @@ def main():
     ap.add_argument("--serve-capacity", type=float, default=None,
                     help="configs/s of a closed run, for --serve-phase open")
     ap.add_argument("--history", type=int, default=8, help="L-BFGS history length of single-configuration quenches")
+    ap.add_argument("--stall-window", type=int, default=None,
+                    help="stall window of single-configuration quenches (default: the library's, 50; FIRE 200)")
     ap.add_argument("--precision", default="dd", choices=("dd", "staged", "fp64"),
                     help="evaluation precision of the quench (staged: FP64 until it stalls, then dd)")
     ap.add_argument("--evals", type=int, default=0,
@@ -304,6 +306,8 @@ def main():
     mopts = dict(s_floor=FLOOR, precision=args.precision, method=args.method, history=args.history)
     if args.method == "fire":
         mopts["stall_window"] = 200
+    if args.stall_window:
+        mopts["stall_window"] = args.stall_window
     # all starting configurations resident in HBM before the timed region
     starts = [torch.from_numpy(inputs.config_positions(wl["cfg_id"], d, N, r)).cuda()
               for r in range(args.warmup + args.steps)]
@@ -421,6 +425,7 @@ def main():
                                + ("" if args.precision == "dd" else f", {args.precision} precision"),
                    "d": d, "N": N, "chi": chi, "R2": w.R2, "M": w.M, "s_floor": FLOOR, "vkind": vkind,
                    "precision": args.precision, "method": args.method, "history": args.history,
+                   "stall_window": mopts.get("stall_window", 50),
                    "parallelism": "single GPU"},
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{args.steps}",

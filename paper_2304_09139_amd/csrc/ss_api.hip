@@ -374,6 +374,35 @@ int64_t rounds_fit(int64_t capacity, int64_t per, int64_t max_steps, int rounds)
   return best;
 }
 
+// XCD-aware launch order of the n(k) units.  Workgroups go to the kXcds XCDs
+// round-robin by linear index, and every unit stages the table rows of its
+// particle range.  The units sorted by first particle are cut into kXcds runs of
+// equal count; run x is dealt to grid positions x, x + kXcds, ... so XCD x
+// works through particles [x N / kXcds, (x + 1) N / kXcds) in order: the units
+// running together on one XCD share particle ranges, and their table rows come
+// from that XCD's L2 instead of once per piece block from memory.  Only the
+// launch order changes (results are the same bits).
+std::vector<NkUnit> xcd_order(std::vector<NkUnit> units) {
+  const size_t n = units.size();
+  if (n < 2 * (size_t)kXcds) return units;
+  std::stable_sort(units.begin(), units.end(), [](const NkUnit& a, const NkUnit& b) {
+    return a.j0 != b.j0 ? a.j0 < b.j0 : a.block < b.block;
+  });
+  std::vector<NkUnit> out(n);
+  const size_t per = (n + kXcds - 1) / kXcds;  // units per XCD run (the last run may be shorter)
+  size_t pos = 0;
+  // position k * kXcds + x takes unit k of run x while every run has one;
+  // the units left after the shortest run ends fill the remaining positions in order
+  std::vector<size_t> next(kXcds);
+  for (int x = 0; x < kXcds; ++x) next[x] = std::min(n, x * per);
+  for (size_t k = 0; pos < n; ++k)
+    for (int x = 0; x < kXcds && pos < n; ++x) {
+      const size_t end = std::min(n, (x + 1) * per);
+      if (next[x] < end) out[pos++] = units[next[x]++];
+    }
+  return out;
+}
+
 // n(k) pass schedule for N particles: exactly kNkRounds rounds of resident
 // blocks in total (fewer only when N is small), apportioned over the piece blocks
 // in proportion to their work per particle (longest piece + base cost), so that
@@ -428,6 +457,7 @@ int nk_schedule(ss_ctx* ctx, Plan* pl, int64_t N, int pt, Plan::NkSched** out) {
     for (size_t q = s0; q < s1; ++q)
       for (int t = 0; t < pl->seg_host[q].len; ++t) rows_of[pl->slot_off.off[t] + q] = (int32_t)Pb;
   }
+  units = xcd_order(std::move(units));
   Plan::NkSched sc;
   sc.nunits = (int64_t)units.size();
   sc.rows = maxrows;
