@@ -429,6 +429,7 @@ def main():
                    "parallelism": "single GPU"},
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{args.steps}",
+        "statuses": sorted({r["status"] for r in results}),
         "staged_precision": staged if staged is None else dict(
             staged, speedup_configs_per_s=staged["configs_per_s"] / (converged / elapsed)),
         "paper_context": "the paper reports S_max ~ 1e-51 and Phi/eps0 ~ 1e-46 at d=2, N=2e6 (double-double, "
