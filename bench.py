@@ -260,6 +260,9 @@ def main():
     ap.add_argument("--serve-phase", default="all", choices=("all", "closed", "open", "sequential"),
                     help="served workloads: run every phase (default) or one: the closed run (all requests at "
                          "once: capacity), the Poisson run at 0.7 x --serve-capacity, or the one-at-a-time path")
+    ap.add_argument("--serve-range", default=None,
+                    help="a:b -- the one-at-a-time phase quenches requests a..b-1 only (the path is sequential, "
+                         "so its time over the whole stream is the sum over ranges)")
     ap.add_argument("--serve-capacity", type=float, default=None,
                     help="configs/s of a closed run, for --serve-phase open")
     ap.add_argument("--history", type=int, default=8, help="L-BFGS history length of single-configuration quenches")
@@ -891,21 +894,24 @@ def bench_serve(args, wl):
         # the same requests quenched one at a time with ss_minimize (same floor)
         import torch
 
-        xs = [torch.from_numpy(inputs.uniform_positions(w.d, w.N, sd)).cuda() for w, sd in zip(works, seeds)]
-        ns = [ctx.wavevectors(w.d, w.R2) for w in works]
+        a, b = (int(v) for v in args.serve_range.split(":")) if args.serve_range else (0, count)
+        sel = list(range(a, min(b, count)))
+        xs = [torch.from_numpy(inputs.uniform_positions(works[i].d, works[i].N, seeds[i])).cuda() for i in sel]
+        ns = [ctx.wavevectors(works[i].d, works[i].R2) for i in sel]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         last = 0.0
-        for q, (w, n, x) in enumerate(zip(works, ns, xs)):
+        for q, (w, n, x) in enumerate(zip([works[i] for i in sel], ns, xs)):
             r = ctx.minimize(w, n, None, x, s_floor=FLOOR)  # the plain path: double-double
             seq_conv += r["status"] == "converged"
             if time.perf_counter() - t1 - last >= 10.0:
                 last = time.perf_counter() - t1
-                print(f"[serve] one at a time: {q + 1}/{count} done, t {last:.1f}s", file=sys.stderr, flush=True)
+                print(f"[serve] one at a time: {q + 1}/{len(sel)} done, t {last:.1f}s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         seq_s = time.perf_counter() - t1
         out_extra["one_at_a_time"] = {"configs_per_s": seq_conv / seq_s, "seconds": seq_s,
-                                      "converged": f"{seq_conv}/{count}", "precision": "dd"}
+                                      "converged": f"{seq_conv}/{len(sel)}", "requests": [a, a + len(sel)],
+                                      "precision": "dd"}
         if cap:
             out_extra["capacity_vs_one_at_a_time"] = cap / (seq_conv / seq_s)
     # the line's value: the Poisson run when there is one, else the closed run
