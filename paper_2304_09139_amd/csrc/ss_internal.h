@@ -114,6 +114,7 @@ constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks p
 #define SS_NK_ROUNDS 3
 #endif
 constexpr int kNkRounds = SS_NK_ROUNDS;     // rounds of resident blocks in a single-launch n(k) pass
+constexpr int64_t kNkMinChunk = 100;        // particles per n(k) unit below which one round fewer is used
 // d = 2 evaluations use the tiled n(k) pass (k_nk2) from R = kNk2MinR on; single
 // launches also from R = kNk2SmallR on when N <= kNk2SmallN, where the piece
 // walk's grid is small (measured: the walk is faster in between, e.g. N = 8000 at

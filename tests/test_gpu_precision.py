@@ -131,6 +131,26 @@ def test_staged_quench_reaches_floor(ctx):
               f"dd iters={rd['iters']} t={rd['seconds']:.3f}s")
 
 
+def test_staged_switch_is_the_fp64_stage(ctx):
+    """The oracle has no staged mode (parity unpinned for the switch rule): the
+    switch is checked against the rule itself.  A staged quench switches where an
+    FP64-only quench with the stage's own stopping parameters (floor
+    max(s_floor, fp64_floor), stop at the first line-search failure) stops, and
+    its double-double stage then reaches the floor."""
+    d, N, chi = 2, 128, 0.4
+    w = ss.Workload.from_chi(d, N, chi)
+    n = ctx.wavevectors(d, w.R2)
+    for seed in range(3):
+        pos = inputs.config_positions(1, d, N, seed)
+        r = ctx.minimize(w, n, None, dev(pos), s_floor=FLOOR, precision="staged")
+        x64 = dev(pos)
+        r64 = ctx.minimize(w, n, None, x64, s_floor=max(FLOOR, ss.DEFAULT_MIN_OPTS["fp64_floor"]),
+                           precision="fp64", max_ls_fail=1)
+        assert r64["iters"] == r["iters_fp64"], (seed, r64, r)
+        assert r64["evals"] == r["evals_fp64"], (seed, r64, r)
+        assert r["status"] == "converged" and r["iters"] > r["iters_fp64"], r
+
+
 def test_staged_weighted_d3(ctx):
     d, N, chi = 3, 400, 0.35
     w = ss.Workload.from_chi(d, N, chi, vkind=1)
