@@ -595,6 +595,26 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const Til
   } else {
     const int64_t capacity = (int64_t)num_cus(ctx) * grad_blocks_per_cu(p->d);
     c->Q = (int)rounds_fit(capacity, pblocks, maxQ, 4);
+    // all Q chunks of a particle block run on one XCD and share its table rows
+    // in that XCD's L2: with at least Qmin chunks, the particle blocks in flight
+    // on an XCD (capacity / kXcds blocks over Q chunks each) keep their table
+    // rows within kGradL2Bytes.  Among Qmin .. 2 Qmin the count that fills the
+    // last round of blocks best is taken.
+    const int64_t rows_bytes = 64 * (int64_t)p->d * c->R1 * 4 * (int64_t)sizeof(double);
+    const int64_t qmin = std::min<int64_t>(maxQ, (capacity / kXcds * rows_bytes + kGradL2Bytes - 1) / kGradL2Bytes);
+    if (c->Q < qmin) {
+      int64_t best = qmin;
+      double best_eff = -1.0;
+      for (int64_t q = qmin; q <= std::min<int64_t>(maxQ, 2 * qmin); ++q) {
+        const int64_t blocks = q * pblocks;
+        const double eff = (double)blocks / (double)(((blocks + capacity - 1) / capacity) * capacity);
+        if (eff > best_eff + 1e-9) {
+          best_eff = eff;
+          best = q;
+        }
+      }
+      c->Q = (int)best;
+    }
   }
   c->combine_blocks = (c->M + kCombK - 1) / kCombK;
   size_t off = 0;

@@ -107,6 +107,11 @@ constexpr int kNkPieces = 256;    // run pieces per n(k) block (one per lane)
 constexpr int kTabRun = 16;       // phase-table exponents per thread (one sin/cos pair each)
 constexpr int kCombK = 32;        // wavevectors per block of the partial combine
 constexpr int kXcds = 8;          // accelerator complex dies (one L2 each); workgroups are dealt round-robin
+#ifndef SS_GRAD_L2_BYTES
+#define SS_GRAD_L2_BYTES (2 << 20)
+#endif
+// table bytes of the gradient pass's particle blocks in flight on one XCD (of its 4 MB L2)
+constexpr int64_t kGradL2Bytes = SS_GRAD_L2_BYTES;
 constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)
 constexpr int64_t kDefaultGradK = 1024;
 constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks per n(k) piece block
