@@ -403,9 +403,9 @@ std::vector<NkUnit> xcd_order(std::vector<NkUnit> units) {
   return out;
 }
 
-// n(k) pass schedule for N particles: exactly kNkRounds rounds of resident
-// blocks in total (one fewer when that would leave fewer than kNkMinChunk
-// particles per unit, and fewer when N is small), apportioned over the piece blocks
+// n(k) pass schedule for N particles: exactly 2 .. kNkRounds rounds of resident
+// blocks in total (the most that leave at least kNkMinChunk particles per unit;
+// fewer units only when N is small), apportioned over the piece blocks
 // in proportion to their work per particle (longest piece + base cost), so that
 // every unit costs about the same and the last round is as full as the first; the
 // P_b particle ranges of block b split [0, N) as evenly as integers allow (their
@@ -420,12 +420,14 @@ int nk_schedule(ss_ctx* ctx, Plan* pl, int64_t N, int pt, Plan::NkSched** out) {
   }
   if (tl_no_alloc) return refuse_alloc(ctx, "the n(k) schedule");
   const size_t nb = pl->block_maxlen.size();
-  // rounds: kNkRounds while the units keep at least kNkMinChunk particles on
-  // average, else one fewer -- every extra round adds partial rows that the
-  // combine pass reads back (d=3, N=8000: 3 rounds cost more in the combine than
-  // they save in the n(k) pass; N=30000: they save 4%)
+  // rounds: the most (2 .. kNkRounds) that keep at least kNkMinChunk particles
+  // per unit on average -- more rounds balance the units' ends better, but every
+  // round adds partial rows that the combine pass reads back (d=3, N=8000: 3
+  // rounds cost more in the combine than they save in the n(k) pass; N=30000:
+  // 3 save 4% against 2; N=60000: 4 save 2.6% against 3)
   const int64_t cap = (int64_t)num_cus(ctx) * nk_blocks_per_cu(pl->d, pt, pl->R + 1);
-  const int rounds = (N * (int64_t)nb >= kNkMinChunk * kNkRounds * cap) ? kNkRounds : std::max(1, kNkRounds - 1);
+  int rounds = kNkRounds;
+  while (rounds > 2 && N * (int64_t)nb < kNkMinChunk * rounds * cap) --rounds;
   const int64_t target = rounds * cap;
   const int64_t maxP = std::max<int64_t>(1, (N + pt - 1) / pt);  // at least pt particles per unit
   double wsum = 0.0;

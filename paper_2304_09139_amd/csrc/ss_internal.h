@@ -116,10 +116,10 @@ constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching 
 constexpr int64_t kDefaultGradK = 1024;
 constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks per n(k) piece block
 #ifndef SS_NK_ROUNDS
-#define SS_NK_ROUNDS 3
+#define SS_NK_ROUNDS 4
 #endif
-constexpr int kNkRounds = SS_NK_ROUNDS;     // rounds of resident blocks in a single-launch n(k) pass
-constexpr int64_t kNkMinChunk = 100;        // particles per n(k) unit below which one round fewer is used
+constexpr int kNkRounds = SS_NK_ROUNDS;     // most rounds of resident blocks in a single-launch n(k) pass
+constexpr int64_t kNkMinChunk = 100;        // fewest particles per n(k) unit (on average) that a round may leave
 // d = 2 evaluations use the tiled n(k) pass (k_nk2) from R = kNk2MinR on; single
 // launches also from R = kNk2SmallR on when N <= kNk2SmallN, where the piece
 // walk's grid is small (measured: the walk is faster in between, e.g. N = 8000 at
