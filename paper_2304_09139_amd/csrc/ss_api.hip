@@ -601,10 +601,12 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const Til
     // in that XCD's L2: with at least Qmin chunks, the particle blocks in flight
     // on an XCD (capacity / kXcds blocks over Q chunks each) keep their table
     // rows within kGradL2Bytes.  Among Qmin .. 2 Qmin the count that fills the
-    // last round of blocks best is taken.
+    // last round of blocks best is taken.  Not when Qmin exceeds kGradMaxQ:
+    // then a particle block's rows alone nearly fill the L2 (d = 2 at large
+    // cutoffs) and more chunks would only add partial rows.
     const int64_t rows_bytes = 64 * (int64_t)p->d * c->R1 * 4 * (int64_t)sizeof(double);
     const int64_t qmin = std::min<int64_t>(maxQ, (capacity / kXcds * rows_bytes + kGradL2Bytes - 1) / kGradL2Bytes);
-    if (c->Q < qmin) {
+    if (c->Q < qmin && qmin <= kGradMaxQ) {
       int64_t best = qmin;
       double best_eff = -1.0;
       for (int64_t q = qmin; q <= std::min<int64_t>(maxQ, 2 * qmin); ++q) {

@@ -112,6 +112,7 @@ constexpr int kXcds = 8;          // accelerator complex dies (one L2 each); wor
 #endif
 // table bytes of the gradient pass's particle blocks in flight on one XCD (of its 4 MB L2)
 constexpr int64_t kGradL2Bytes = SS_GRAD_L2_BYTES;
+constexpr int64_t kGradMaxQ = 32;  // the largest chunk count that rule may ask for
 constexpr int64_t kDefaultNkChunk = 64;   // batched tile defaults (no matching tile entry)
 constexpr int64_t kDefaultGradK = 1024;
 constexpr int64_t kMaxNkRows = 256;         // built-in shape: particle chunks per n(k) piece block
