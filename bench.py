@@ -256,7 +256,7 @@ def main():
     ap.add_argument("--mp-report", action="store_true",
                     help="report the 256-bit error of n~ at sampled k of the final configuration")
     ap.add_argument("--method", default="lbfgs", choices=("lbfgs", "fire"),
-                    help="minimiser of the single-configuration quench")
+                    help="minimiser of the single-configuration and batched quenches")
     ap.add_argument("--serve-phase", default="all", choices=("all", "closed", "open", "sequential"),
                     help="served workloads: run every phase (default) or one: the closed run (all requests at "
                          "once: capacity), the Poisson run at 0.7 x --serve-capacity, or the one-at-a-time path")
@@ -695,7 +695,9 @@ def bench_batch(args, wl):
     steps = args.steps if args.steps_set else 2
     starts = [[torch.from_numpy(inputs.config_positions(wl["cfg_id"], w.d, w.N, 1000 * r + i)).cuda()
                for i, w in enumerate(works)] for r in range(args.warmup + steps)]
-    opts = dict(s_floor=FLOOR, precision=args.precision)
+    opts = dict(s_floor=FLOOR, precision=args.precision, method=args.method)
+    if args.method == "fire":
+        opts["stall_window"] = 200
     need = ctx.batch_workspace_size(works, [dict(ss.DEFAULT_MIN_OPTS, **opts)] * count)
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
@@ -766,12 +768,15 @@ def bench_batch(args, wl):
         "vs_baseline": None,
         "dtype": {"dd": "dd", "staged": "f64 then dd", "fp64": "f64"}[args.precision],
         "data": "synthetic (seeded uniform-random starts, the paper's Poisson initial condition)",
-        "config": {"workload": f"batched L-BFGS quenches to S_max <= {FLOOR:g}: {count} configurations, "
+        "config": {"workload": f"batched {'FIRE' if args.method == 'fire' else 'L-BFGS'} quenches to "
+                               f"S_max <= {FLOOR:g}: {count} configurations, "
                                f"d in {{2,3}}, N log-uniform in [500, 5000], chi in {{0.2, 0.35, 0.45}}, v(k)=1"
                                + ("" if args.precision == "dd" else f", {args.precision} precision"),
-                   "configs": count, "s_floor": FLOOR, "precision": args.precision, "parallelism": "single GPU"},
+                   "configs": count, "s_floor": FLOOR, "precision": args.precision, "method": args.method,
+                   "parallelism": "single GPU"},
         "configs_per_s": converged / elapsed,
         "converged": f"{converged}/{len(results)}",
+        "iters_mean": sum(r["iters"] for r in results) / len(results),
         "fp64_pairs_per_s": pairs64 / elapsed,
         "staged_precision": None if staged is None else dict(
             staged, speedup_vs_one_at_a_time_dd=None if args.no_sequential else
