@@ -691,6 +691,7 @@ def bench_batch(args, wl):
 
     ctx_tuned = bool(load_tiles())
     ctx = ss.Context(0, tiles="tuned")
+    ctx.progress(args.progress)
     works = [ss.Workload.from_chi(d, N, chi) for d, N, chi in shapes]
     steps = args.steps if args.steps_set else 2
     starts = [[torch.from_numpy(inputs.config_positions(wl["cfg_id"], w.d, w.N, 1000 * r + i)).cuda()
