@@ -261,8 +261,9 @@ def main():
                     help="served workloads: run every phase (default) or one: the closed run (all requests at "
                          "once: capacity), the Poisson run at 0.7 x --serve-capacity, or the one-at-a-time path")
     ap.add_argument("--serve-range", default=None,
-                    help="a:b -- the one-at-a-time phase quenches requests a..b-1 only (the path is sequential, "
-                         "so its time over the whole stream is the sum over ranges)")
+                    help="a:b -- the chosen phase runs requests a..b-1 of the stream only (one at a time: the "
+                         "time over the stream is the sum over ranges; Poisson: a window of the stream with its "
+                         "own arrival gaps, from an empty server)")
     ap.add_argument("--serve-capacity", type=float, default=None,
                     help="configs/s of a closed run, for --serve-phase open")
     ap.add_argument("--history", type=int, default=8, help="L-BFGS history length of single-configuration quenches")
@@ -815,13 +816,14 @@ def bench_serve(args, wl):
     # seed itself (the same positions as inputs.config_positions)
     seeds = [inputs.stream_seed(wl["cfg_id"], i) for i in range(count)]
     ctx = ss.Context(0, tiles="tuned")
+    ctx.progress(args.progress)  # progress lines of single quenches (one-at-a-time phase)
     arena = wl.get("arena_gb", 8) << 30
     ctx.server_start(arena, max_slots=512)
 
     trace = []
 
-    def run(times):
-        """Submit request i at times[i] (seconds from the start), collect all;
+    def run(times, sel):
+        """Submit request sel[i] at times[i] (seconds from the start), collect all;
         the server's running and queued counts are sampled every 0.25 s."""
         trace.clear()
         t0 = time.perf_counter()
@@ -830,13 +832,15 @@ def bench_serve(args, wl):
         done = {}
         i = 0
         last = 0.0
-        while len(done) < count:
+        n = len(sel)
+        while len(done) < n:
             now = time.perf_counter() - t0
-            while i < count and times[i] <= now:
-                tickets.append(ctx.submit(works[i], None, seed=seeds[i], s_floor=FLOOR, precision=args.precision))
+            while i < n and times[i] <= now:
+                r = sel[i]
+                tickets.append(ctx.submit(works[r], None, seed=seeds[r], s_floor=FLOOR, precision=args.precision))
                 i += 1
                 if i % 25 == 0 and times[i - 1] == 0.0:
-                    print(f"[serve] {i}/{count} submitted, t {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+                    print(f"[serve] {i}/{n} submitted, t {time.perf_counter() - t0:.1f}s", file=sys.stderr,
                           flush=True)
             for k, t in enumerate(tickets):
                 if k not in done:
@@ -849,9 +853,9 @@ def bench_serve(args, wl):
                 trace.append((t_sample, st["running"], st["queued"]))
             if time.perf_counter() - t0 - last >= 10.0:  # a progress line every 10 s
                 last = time.perf_counter() - t0
-                print(f"[serve] {len(done)}/{count} done, {i} submitted, t {last:.1f}s", file=sys.stderr, flush=True)
+                print(f"[serve] {len(done)}/{n} done, {i} submitted, t {last:.1f}s", file=sys.stderr, flush=True)
             time.sleep(0.0005)
-        return time.perf_counter() - t0, [done[k] for k in range(count)]
+        return time.perf_counter() - t0, [done[k] for k in range(n)]
 
     # warm-up: a few short requests of the smallest configurations (server
     # buffers, first launches)
@@ -873,10 +877,15 @@ def bench_serve(args, wl):
         return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "max": float(lat.max())}
 
     phase = args.serve_phase
-    out_extra = {}
+    # --serve-range a:b runs the chosen phase on requests a..b-1 of the stream (a
+    # window of the Poisson stream keeps its own arrival gaps, from an empty server)
+    a, b = (int(v) for v in args.serve_range.split(":")) if args.serve_range else (0, count)
+    sel = list(range(a, min(b, count)))
+    sel_works = [works[i] for i in sel]
+    out_extra = {"requests": [sel[0], sel[-1] + 1]} if args.serve_range else {}
     closed, opened, cap, closed_s, open_s, lam = None, None, args.serve_capacity, None, None, None
     if phase in ("all", "closed"):
-        closed_s, closed = run([0.0] * count)
+        closed_s, closed = run([0.0] * len(sel), sel)
         print(f"[serve] closed run: {closed_s:.1f}s", file=sys.stderr, flush=True)
         cap = sum(1 for r in closed if r["status"] == "converged") / closed_s
         out_extra["occupancy_closed"] = occupancy(trace)
@@ -884,31 +893,31 @@ def bench_serve(args, wl):
         out_extra["closed_batch_latency_s"] = latency(closed)
         # where the time goes: the share of the pair work in the requests with N >= 2e4
         out_extra["pair_work_share_N_ge_2e4"] = (
-            sum(w.M * w.N * r["evals"] for w, r in zip(works, closed) if w.N >= 20000)
-            / max(1, sum(w.M * w.N * r["evals"] for w, r in zip(works, closed))))
+            sum(w.M * w.N * r["evals"] for w, r in zip(sel_works, closed) if w.N >= 20000)
+            / max(1, sum(w.M * w.N * r["evals"] for w, r in zip(sel_works, closed))))
     if phase in ("all", "open"):
         if not cap:
             raise SystemExit("--serve-phase open needs --serve-capacity (configs/s of the closed run)")
         lam = 0.7 * cap
-        open_s, opened = run([t / lam for *_, t in stream])
+        t_start = stream[sel[0] - 1][3] if sel[0] > 0 else 0.0
+        open_s, opened = run([(stream[i][3] - t_start) / lam for i in sel], sel)
         out_extra["occupancy_poisson"] = occupancy(trace)
         out_extra["latency_s"] = latency(opened)
     out_extra["server_counters_total"] = ctx.server_stats()
     ctx.server_stop()
     seq_conv, seq_s = 0, float("nan")
     if phase in ("all", "sequential") and not args.no_sequential:
-        # the same requests quenched one at a time with ss_minimize (same floor)
+        # the same requests quenched one at a time with ss_minimize (same floor and
+        # precision)
         import torch
 
-        a, b = (int(v) for v in args.serve_range.split(":")) if args.serve_range else (0, count)
-        sel = list(range(a, min(b, count)))
         xs = [torch.from_numpy(inputs.uniform_positions(works[i].d, works[i].N, seeds[i])).cuda() for i in sel]
         ns = [ctx.wavevectors(works[i].d, works[i].R2) for i in sel]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         last = 0.0
         for q, (w, n, x) in enumerate(zip([works[i] for i in sel], ns, xs)):
-            r = ctx.minimize(w, n, None, x, s_floor=FLOOR)  # the plain path: double-double
+            r = ctx.minimize(w, n, None, x, s_floor=FLOOR, precision=args.precision)
             seq_conv += r["status"] == "converged"
             if time.perf_counter() - t1 - last >= 10.0:
                 last = time.perf_counter() - t1
@@ -917,14 +926,14 @@ def bench_serve(args, wl):
         seq_s = time.perf_counter() - t1
         out_extra["one_at_a_time"] = {"configs_per_s": seq_conv / seq_s, "seconds": seq_s,
                                       "converged": f"{seq_conv}/{len(sel)}", "requests": [a, a + len(sel)],
-                                      "precision": "dd"}
+                                      "precision": args.precision}
         if cap:
             out_extra["capacity_vs_one_at_a_time"] = cap / (seq_conv / seq_s)
     # the line's value: the Poisson run when there is one, else the closed run
     res, el = (opened, open_s) if opened is not None else (closed, closed_s)
     if res is None:
         res, el = [], float("nan")
-    pairs = sum(w.M * w.N * (r["evals"] - r["evals_fp64"]) for w, r in zip(works, res))
+    pairs = sum(w.M * w.N * (r["evals"] - r["evals_fp64"]) for w, r in zip(sel_works, res))
     conv = sum(1 for r in res if r["status"] == "converged")
     out = {
         "metric": "dd particle-wavevector pairs/s (Phi+grad) and configs/s at stated max S(k) floor",
@@ -943,7 +952,8 @@ def bench_serve(args, wl):
                                f"N log-uniform in [{n_min}, {n_max}], chi uniform in [0.1, 0.49]"
                                + (", Poisson arrivals at 0.7 x capacity" if opened is not None else
                                   ", all submitted at once" if closed is not None else "")
-                               + ("" if args.precision == "dd" else f", {args.precision} precision"),
+                               + ("" if args.precision == "dd" else f", {args.precision} precision")
+                               + (f", requests {sel[0]}..{sel[-1]} of the stream" if args.serve_range else ""),
                    "requests": count, "s_floor": FLOOR, "precision": args.precision, "phase": phase,
                    "parallelism": "single GPU"},
         "configs_per_s": conv / el if res else None,
