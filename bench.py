@@ -915,13 +915,14 @@ def bench_serve(args, wl):
         ns = [ctx.wavevectors(works[i].d, works[i].R2) for i in sel]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        last = 0.0
         for q, (w, n, x) in enumerate(zip([works[i] for i in sel], ns, xs)):
+            tq = time.perf_counter()
             r = ctx.minimize(w, n, None, x, s_floor=FLOOR, precision=args.precision)
             seq_conv += r["status"] == "converged"
-            if time.perf_counter() - t1 - last >= 10.0:
-                last = time.perf_counter() - t1
-                print(f"[serve] one at a time: {q + 1}/{len(sel)} done, t {last:.1f}s", file=sys.stderr, flush=True)
+            # one line per request: a window cut short still says what it finished
+            print(f"[serve] one at a time: request {sel[q]} d={w.d} N={w.N} {r['status']} "
+                  f"{time.perf_counter() - tq:.2f}s ({q + 1}/{len(sel)}, t {time.perf_counter() - t1:.1f}s)",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         seq_s = time.perf_counter() - t1
         out_extra["one_at_a_time"] = {"configs_per_s": seq_conv / seq_s, "seconds": seq_s,
