@@ -35,12 +35,14 @@ if ROOT not in sys.path:
 
 FLOOR = 1e-40
 # FP64 operations per particle-wavevector pair in the inner loops, counted from
-# the kernel source as (add, mul, fma).  The n~(k) pass does one lazy complex dd
-# product (two lazy dd dot products of 8 add, 2 mul, 6 fma each) and two lazy dd
-# accumulations (8 add each); the gradient pass does the complex product, the
-# lazy dd dot product v (S c - C s) and two lazy accumulations (the sum of q and
-# the sum of its prefix sums).
-OPS_PER_PAIR_MIX = {"nk": (32, 4, 12), "grad": (40, 6, 18)}
+# the kernel source as (add, mul, fma).  The n~(k) pass forms b z^t and b conj(z^t)
+# for two wavevectors from four shared lazy dd products (4 mul, 12 fma) and four
+# TwoSums with their error terms (32 add), and adds each pair factor with two
+# lazy dd accumulations (8 add each): per pair 16 + 16 add, 2 mul, 6 fma; the
+# gradient pass does a lazy complex dd product (two lazy dd dot products of 8 add,
+# 2 mul, 6 fma each), the lazy dd dot product v (S c - C s) and two lazy
+# accumulations (the sum of q and the sum of its prefix sums).
+OPS_PER_PAIR_MIX = {"nk": (32, 2, 6), "grad": (40, 6, 18)}
 # operations counted once (issue slots) and floating-point operations with an
 # FMA counted as two (the convention of the published FP64 peak)
 OPS_PER_PAIR = {k: a + m + f for k, (a, m, f) in OPS_PER_PAIR_MIX.items()}

@@ -227,18 +227,32 @@ int build_plan_lists(ss_ctx* ctx, Plan* pl) {
       runs.push_back(s);
     }
   }
-  // pieces of at most kSegLen, balanced within a run, longest first
+  // pieces of the n(k) pass (see nk_body): a run with a nonzero prefix is a
+  // symmetric column, last component -h .. h, and its pieces take exponents
+  // t0 .. t0 + L - 1 of 0 .. h with their negatives (2L stored wavevectors, 2L - 1
+  // for t0 = 0); the prefix-zero run (0, .., 0, t), t = 1 .. R, takes t alone.
+  // At most kSegLen / 2 exponents per piece, balanced within a run.  A piece's k0
+  // is the walk position that last component 0 has (or would have) in its run,
+  // so that the wavevector with last component x sits at k0 + x.
+  constexpr int kMaxT = kSegLen / 2;
   std::vector<Span> segs;
   for (const Span& r : runs) {
-    const int pieces = (r.len + kSegLen - 1) / kSegLen;
-    const int base = r.len / pieces, extra = r.len % pieces;
+    bool plus = true;
+    for (int a = 0; a < d - 1; ++a) plus = plus && r.n[a] == 0;
+    const int first = r.n[d - 1];
+    const int t_lo = plus ? first : 0;
+    const int T = plus ? r.len : -first + 1;  // exponents of the run
+    if (!plus && r.len != 2 * T - 1) return set_err(ctx, SS_EHIP, "a column of the half set is not symmetric");
+    const int pieces = (T + kMaxT - 1) / kMaxT;
+    const int base = T / pieces, extra = T % pieces;
     int off = 0;
     for (int i = 0; i < pieces; ++i) {
       Span s = r;
-      s.k0 = r.k0 + off;
-      s.len = base + (i < extra ? 1 : 0);
-      s.n[d - 1] = (int16_t)(r.n[d - 1] + off);
-      off += s.len;
+      const int L = base + (i < extra ? 1 : 0);
+      s.k0 = r.k0 - first;
+      s.n[d - 1] = (int16_t)(t_lo + off);
+      s.len = plus ? L : (t_lo + off == 0 ? 2 * L - 1 : 2 * L);
+      off += L;
       segs.push_back(s);
     }
   }
@@ -259,11 +273,29 @@ int build_plan_lists(ss_ctx* ctx, Plan* pl) {
     }
     if (acc != M) return set_err(ctx, SS_EHIP, "piece slots do not cover the wavevectors");
     std::vector<int32_t> kos((size_t)M, -1);
-    for (size_t q = 0; q < segs.size(); ++q)
-      for (int t = 0; t < segs[q].len; ++t) {
+    for (size_t q = 0; q < segs.size(); ++q) {
+      const Span& sg = segs[q];
+      bool plus = true;
+      for (int a = 0; a < d - 1; ++a) plus = plus && sg.n[a] == 0;
+      const int t0 = sg.n[d - 1];
+      for (int t = 0; t < sg.len; ++t) {
         if ((int64_t)q >= cnt[t]) return set_err(ctx, SS_EHIP, "pieces are not sorted by length");
-        kos[pl->slot_off.off[t] + q] = segs[q].k0 + t;
+        // stored index t -> accumulator acc (nk_body) -> last component x
+        const int acc = plus ? 2 * t : (t0 == 0 && t >= 1 ? t + 1 : t);
+        const int x = acc % 2 == 0 ? t0 + acc / 2 : -(t0 + acc / 2);
+        const int64_t k = (int64_t)sg.k0 + x;
+        if (k < 0 || k >= M || kos[pl->slot_off.off[t] + q] != -1)
+          return set_err(ctx, SS_EHIP, "piece slots do not map onto the wavevectors");
+        kos[pl->slot_off.off[t] + q] = (int32_t)k;
       }
+    }
+    {
+      std::vector<char> seen((size_t)M, 0);
+      for (int32_t k : kos) {
+        if (k < 0 || seen[k]) return set_err(ctx, SS_EHIP, "piece slots do not map onto the wavevectors");
+        seen[k] = 1;
+      }
+    }
     SS_HIP(ctx, hipMalloc(&pl->k_of_slot, sizeof(int32_t) * M));
     SS_HIP(ctx, hipMemcpy(pl->k_of_slot, kos.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
   }

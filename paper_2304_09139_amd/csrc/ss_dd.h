@@ -166,6 +166,38 @@ __device__ __forceinline__ cdd cmul(const cdd& a, const cdd& b) {
 
 __device__ __forceinline__ cdd cconj(const cdd& a) { return cdd{a.rh, a.rl, -a.ih, -a.il}; }
 
+// plus = b u and minus = b conj(u) for complex dd of modulus O(1).  The two
+// products share the four real products br ur, bi ui, br ui, bi ur (4
+// operations each: the high product, its rounding error by FMA and the two
+// cross terms); each component is then one TwoSum of two of them plus the
+// error terms (8).  48 operations for the pair against 64 for two cmul.
+__device__ __forceinline__ void cmul_pm(const cdd& b, const cdd& u, cdd& plus, cdd& minus) {
+  const double p1 = b.rh * u.rh;
+  double e1 = __builtin_fma(b.rh, u.rh, -p1);
+  e1 = __builtin_fma(b.rh, u.rl, e1);
+  e1 = __builtin_fma(b.rl, u.rh, e1);
+  const double p2 = b.ih * u.ih;
+  double e2 = __builtin_fma(b.ih, u.ih, -p2);
+  e2 = __builtin_fma(b.ih, u.il, e2);
+  e2 = __builtin_fma(b.il, u.ih, e2);
+  const double p3 = b.rh * u.ih;
+  double e3 = __builtin_fma(b.rh, u.ih, -p3);
+  e3 = __builtin_fma(b.rh, u.il, e3);
+  e3 = __builtin_fma(b.rl, u.ih, e3);
+  const double p4 = b.ih * u.rh;
+  double e4 = __builtin_fma(b.ih, u.rh, -p4);
+  e4 = __builtin_fma(b.ih, u.rl, e4);
+  e4 = __builtin_fma(b.il, u.rh, e4);
+  two_sum(p1, -p2, plus.rh, plus.rl);  // re(b u) = br ur - bi ui
+  plus.rl += e1 - e2;
+  two_sum(p3, p4, plus.ih, plus.il);  // im(b u) = br ui + bi ur
+  plus.il += e3 + e4;
+  two_sum(p1, p2, minus.rh, minus.rl);  // re(b conj u) = br ur + bi ui
+  minus.rl += e1 + e2;
+  two_sum(p4, -p3, minus.ih, minus.il);  // im(b conj u) = bi ur - br ui
+  minus.il += e4 - e3;
+}
+
 // accumulator: acc += (xh, xl) without renormalising acc (8 ops)
 __device__ __forceinline__ void lazy_acc(double& ah, double& al, double xh, double xl) {
   double s, e;

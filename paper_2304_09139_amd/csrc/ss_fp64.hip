@@ -11,9 +11,10 @@
 // zero low words, so the minimiser is unchanged.
 //
 // Error: every table entry carries a relative error <= 2^-53; a term is a
-// product of at most D - 1 + len of them (len <= kSegLen in the n(k) pass, the
-// run length in the gradient pass), so |term error| <= (D + len + 1) 2^-53 and
-// the N-term sums add N rounding errors of their own.
+// product of at most D of them in the n(k) pass (the prefix entries and one
+// z^t) and of D - 1 + len in the gradient pass (len the run length), so
+// |term error| <= (D + len + 1) 2^-53 with len = 1 in the n(k) pass, and the
+// N-term sums add N rounding errors of their own.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,23 +39,33 @@ __device__ __forceinline__ c64 lds64_entry(const double* tp, int R1, int a, int 
   return c64{e[0], m < 0 ? -e[1] : e[1]};
 }
 
-// the staged particles of one tile, every lane walking the wave's longest piece
-// (L wavevectors) fully unrolled (terms past a lane's own piece are not stored)
+// the staged particles of one tile, every lane taking the L exponents of the
+// wave's widest piece (terms past a lane's own piece are not stored): per
+// particle the prefix product b, then b z^t and b conj(z^t) into accumulators
+// 2i and 2i + 1 (the pieces, accumulators and slots of the double-double pass)
 template <int D, int L>
 __device__ __forceinline__ void nk64_tile(const double* __restrict__ lds, int np, int epp, int R1, const Span& sg,
                                           double (&cr)[kSegLen], double (&ci)[kSegLen]) {
+  const int t0 = sg.n[D - 1];
 #pragma unroll 1
   for (int p = 0; p < np; ++p) {
     const double* tp = lds + p * epp;
-    c64 w = lds64_entry(tp, R1, D - 1, sg.n[D - 1]);
+    c64 b{1.0, 0.0};
+    if constexpr (D > 1) {
+      b = lds64_entry(tp, R1, 0, sg.n[0]);
 #pragma unroll
-    for (int a = 0; a < D - 1; ++a) w = cmul64(w, lds64_entry(tp, R1, a, sg.n[a]));
-    const c64 z = lds64_entry(tp, R1, D - 1, 1);
+      for (int a = 1; a < D - 1; ++a) b = cmul64(b, lds64_entry(tp, R1, a, sg.n[a]));
+    }
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      cr[t] += w.re;
-      ci[t] += w.im;
-      if (t + 1 < L) w = cmul64(w, z);
+    for (int i = 0; i < L; ++i) {
+      const int m = t0 + i < R1 ? t0 + i : R1 - 1;
+      const double* e = tp + ((D - 1) * R1 + m) * 2;
+      const double ur = e[0], ui = e[1];
+      const double ii = b.im * ui, ri = b.re * ui, ir = b.im * ur;
+      cr[2 * i] += __builtin_fma(b.re, ur, -ii);
+      ci[2 * i] += __builtin_fma(b.re, ui, ir);
+      cr[2 * i + 1] += __builtin_fma(b.re, ur, ii);
+      ci[2 * i + 1] += __builtin_fma(b.im, ur, -ri);
     }
   }
 }
@@ -70,11 +81,19 @@ __device__ __forceinline__ void nk64_body(const Span* __restrict__ segs, int64_t
   const Span sg = segs[s < nseg ? s : nseg - 1];
   const int len = s < nseg ? sg.len : 0;
   const int epp = D * R1 * 2;  // doubles per particle
+  bool plus = true;  // the prefix-zero column
+#pragma unroll
+  for (int a = 0; a < D - 1; ++a) plus = plus && sg.n[a] == 0;
+  const bool zero = !plus && sg.n[D - 1] == 0;
+  const int nt = plus ? len : (len + 1) / 2;  // exponents of this lane's piece
   double cr[kSegLen], ci[kSegLen];
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) cr[t] = ci[t] = 0.0;
-  // pieces are sorted longest first: lane 0 holds the wave's longest piece
-  const int wl = __builtin_amdgcn_readfirstlane(len);
+  // the widest piece of the wave, in a scalar register, selects the unrolled loop
+  int wmax = nt;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o));
+  const int wl = __builtin_amdgcn_readfirstlane(wmax);
   for (int64_t tile = u.j0; tile < u.j1; tile += PT) {
     const int np = (int)((u.j1 - tile) < PT ? (u.j1 - tile) : PT);
     __syncthreads();
@@ -86,11 +105,9 @@ __device__ __forceinline__ void nk64_body(const Span* __restrict__ segs, int64_t
     }
     __syncthreads();
     switch (wl) {
-      case 8: nk64_tile<D, 8>(lds, np, epp, R1, sg, cr, ci); break;
-      case 7: nk64_tile<D, 7>(lds, np, epp, R1, sg, cr, ci); break;
-      case 6: nk64_tile<D, 6>(lds, np, epp, R1, sg, cr, ci); break;
-      case 5: nk64_tile<D, 5>(lds, np, epp, R1, sg, cr, ci); break;
-      case 4: nk64_tile<D, 4>(lds, np, epp, R1, sg, cr, ci); break;
+      case 4:
+        if constexpr (kSegLen >= 8) nk64_tile<D, 4>(lds, np, epp, R1, sg, cr, ci);
+        break;
       case 3: nk64_tile<D, 3>(lds, np, epp, R1, sg, cr, ci); break;
       case 2: nk64_tile<D, 2>(lds, np, epp, R1, sg, cr, ci); break;
       case 1: nk64_tile<D, 1>(lds, np, epp, R1, sg, cr, ci); break;
@@ -102,8 +119,13 @@ __device__ __forceinline__ void nk64_body(const Span* __restrict__ segs, int64_t
   for (int t = 0; t < kSegLen; ++t) {
     if (t < len) {
       const int64_t slot = so.off[t] + s;
-      out[slot] = cr[t];
-      out[M + slot] = ci[t];
+      constexpr int kLast = kSegLen - 1;
+      const int q1 = t + 1 < kLast ? t + 1 : kLast, q2 = 2 * t < kLast ? 2 * t : kLast;
+      double vr = cr[t], vi = ci[t];
+      if (zero && t >= 1) vr = cr[q1], vi = ci[q1];
+      if (plus) vr = cr[q2], vi = ci[q2];
+      out[slot] = vr;
+      out[M + slot] = vi;
     }
   }
 }

@@ -29,6 +29,7 @@ struct NkUnit {
 };
 
 constexpr int kSegLen = 8;        // wavevectors per lane in the n(k) pass
+static_assert(kSegLen % 2 == 0, "an n(k) piece stores exponents in +/- pairs");
 
 // Slot order of the n(k) partials: pieces are sorted by length (longest first),
 // so the pieces longer than t are a prefix 0 .. cnt_t - 1 of the piece list;

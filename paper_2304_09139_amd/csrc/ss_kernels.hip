@@ -12,11 +12,12 @@
 //   * k_table      builds z_{j,a}^m for m = 0..R by an exact reduction of
 //                  m u mod 1 and a double-double sin/cos (the only
 //                  transcendental work, O(d R N));
-//   * k_nk         runs the n~(k) reduction.  Each lane owns up to kSegLen
-//                  consecutive wavevectors of one column (fixed n_0..n_{d-2})
-//                  and walks them with one complex dd product per pair,
-//                  looping over a particle chunk whose tables are staged in
-//                  LDS;
+//   * k_nk         runs the n~(k) reduction.  Each lane owns a piece of one
+//                  column (fixed n_0..n_{d-2}): up to kSegLen / 2 exponents t
+//                  of the last axis and, where the column is symmetric, their
+//                  negatives.  Per particle of a chunk whose tables are staged
+//                  in LDS it forms the prefix b = prod z_a^{n_a} once and, for
+//                  each t, b z^t and b conj(z^t) from four shared real products;
 //   * k_nk2        (d = 2, large cutoffs) computes a 16 x 16 tile of
 //                  wavevectors as products of two staged 16-row table slices;
 //   * k_nk_combine sums the chunk partials in a fixed order with the accurate
@@ -84,31 +85,59 @@ __device__ __forceinline__ cdd lds_entry(const double* tp, int R1, int a, int m)
 }
 
 // ---------------------------------------------------------------------------
-// n~(k) partial sums.  One block per unit (a block of kNkPieces run pieces, one
-// per lane, over a particle range [j0, j1)); the particle tables of the range are
-// staged through LDS PT particles at a time and every lane walks its piece over
-// every staged particle.
-// part[((row * 4) + c) * M + k], c = (C.hi, C.lo, S.hi, S.lo), k in walk order.
+// n~(k) partial sums.  One block per unit (a block of kNkPieces pieces, one per
+// lane, over a particle range [j0, j1)); the particle tables of the range are
+// staged through LDS PT particles at a time and every lane evaluates its piece
+// over every staged particle.
+// part[((row * 4) + c) * M + slot], c = (C.hi, C.lo, S.hi, S.lo), slot order.
+//
+// A piece is one column of H (a fixed prefix n_0 .. n_{d-2}) and exponents
+// t = t0 .. t0 + L - 1 of its last axis (L <= kSegLen / 2).  Where the prefix is
+// nonzero the column takes every last component in [-h, h], and the lane also
+// takes the negatives -t: with b = prod_{a < d-1} z_a^{n_a} and u = z_{d-1}^t
+// from the table, the two factors are b u and b conj(u), which share their four
+// real products (cmul_pm).  Accumulators 2i and 2i + 1 hold t0 + i and -(t0 + i).
+// Stored index i of the piece (slot off[i] + lane) holds accumulator
+//   i      where t0 > 0,
+//   0, i + 1 (i >= 1) where t0 = 0 (accumulator 1, "-0", repeats t = 0),
+//   2 i    in the prefix-zero column (0, .., 0, t), t >= 1, whose negatives
+//          are outside H.
 // ---------------------------------------------------------------------------
-// the staged particles of one tile for a wave whose longest piece has L
-// wavevectors: every lane walks L steps (lanes with shorter pieces compute terms
-// they never store), fully unrolled with no per-lane branches
+// the staged particles of one tile for a wave whose widest piece spans L
+// exponents: every lane takes L exponents (lanes with narrower pieces compute
+// terms they never store; exponents past R are clamped into the table), fully
+// unrolled with no per-lane branches
 template <int D, int L>
 __device__ __forceinline__ void nk_tile(const double* __restrict__ lds, int np, int epp, int R1, const Span& sg,
                                         double (&crh)[kSegLen], double (&crl)[kSegLen], double (&cih)[kSegLen],
                                         double (&cil)[kSegLen]) {
+  const int t0 = sg.n[D - 1];
 #pragma unroll 1
   for (int p = 0; p < np; ++p) {
     const double* tp = lds + p * epp;
-    cdd w = lds_entry(tp, R1, D - 1, sg.n[D - 1]);
+    cdd b{1.0, 0.0, 0.0, 0.0};
+    if constexpr (D > 1) {
+      b = lds_entry(tp, R1, 0, sg.n[0]);
 #pragma unroll
-    for (int a = 0; a < D - 1; ++a) w = cmul(w, lds_entry(tp, R1, a, sg.n[a]));
-    const cdd z = lds_entry(tp, R1, D - 1, 1);
+      for (int a = 1; a < D - 1; ++a) b = cmul(b, lds_entry(tp, R1, a, sg.n[a]));
+    }
+    // the entries z^t are read one exponent ahead of their products
+    auto uent = [&](int i) {
+      const int m = t0 + i < R1 ? t0 + i : R1 - 1;
+      const double* e = tp + ((D - 1) * R1 + m) * 4;
+      return cdd{e[0], e[1], e[2], e[3]};
+    };
+    cdd un = uent(0);
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      lazy_acc(crh[t], crl[t], w.rh, w.rl);
-      lazy_acc(cih[t], cil[t], w.ih, w.il);
-      if (t + 1 < L) w = cmul(w, z);
+    for (int i = 0; i < L; ++i) {
+      const cdd u = un;
+      if (i + 1 < L) un = uent(i + 1);
+      cdd wp, wm;
+      cmul_pm(b, u, wp, wm);
+      lazy_acc(crh[2 * i], crl[2 * i], wp.rh, wp.rl);
+      lazy_acc(cih[2 * i], cil[2 * i], wp.ih, wp.il);
+      lazy_acc(crh[2 * i + 1], crl[2 * i + 1], wm.rh, wm.rl);
+      lazy_acc(cih[2 * i + 1], cil[2 * i + 1], wm.ih, wm.il);
     }
   }
 }
@@ -123,14 +152,21 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
   const Span sg = segs[s < nseg ? s : nseg - 1];
   const int len = s < nseg ? sg.len : 0;
   const int epp = D * R1 * 4;  // doubles per particle
+  bool plus = true;  // the prefix-zero column
+#pragma unroll
+  for (int a = 0; a < D - 1; ++a) plus = plus && sg.n[a] == 0;
+  const bool zero = !plus && sg.n[D - 1] == 0;
+  const int nt = plus ? len : (len + 1) / 2;  // exponents of this lane's piece
 
   double crh[kSegLen], crl[kSegLen], cih[kSegLen], cil[kSegLen];
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) crh[t] = crl[t] = cih[t] = cil[t] = 0.0;
 
-  // pieces are sorted longest first, so lane 0 of each wave holds the wave's
-  // longest piece: its length, in a scalar register, selects the unrolled walk
-  const int wl = __builtin_amdgcn_readfirstlane(len);
+  // the widest piece of the wave, in a scalar register, selects the unrolled loop
+  int wmax = nt;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o));
+  const int wl = __builtin_amdgcn_readfirstlane(wmax);
   const int64_t j0 = u.j0;
   const int64_t j1 = u.j1;
   for (int64_t tile = j0; tile < j1; tile += PT) {
@@ -143,11 +179,9 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
     }
     __syncthreads();
     switch (wl) {
-      case 8: nk_tile<D, 8>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
-      case 7: nk_tile<D, 7>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
-      case 6: nk_tile<D, 6>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
-      case 5: nk_tile<D, 5>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
-      case 4: nk_tile<D, 4>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
+      case 4:
+        if constexpr (kSegLen >= 8) nk_tile<D, 4>(lds, np, epp, R1, sg, crh, crl, cih, cil);
+        break;
       case 3: nk_tile<D, 3>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
       case 2: nk_tile<D, 2>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
       case 1: nk_tile<D, 1>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
@@ -159,16 +193,21 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
       renorm(cih[t], cil[t]);
     }
   }
-  // slot order: for each t the lanes of a wave write consecutive slots
+  // slot order: for each stored index the lanes of a wave write consecutive slots
   double* out = part + (int64_t)u.row * 4 * M;
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) {
     if (t < len) {
+      constexpr int kLast = kSegLen - 1;
+      const int q1 = t + 1 < kLast ? t + 1 : kLast, q2 = 2 * t < kLast ? 2 * t : kLast;
+      double vrh = crh[t], vrl = crl[t], vih = cih[t], vil = cil[t];
+      if (zero && t >= 1) vrh = crh[q1], vrl = crl[q1], vih = cih[q1], vil = cil[q1];
+      if (plus) vrh = crh[q2], vrl = crl[q2], vih = cih[q2], vil = cil[q2];
       const int64_t slot = so.off[t] + s;
-      out[slot] = crh[t];
-      out[M + slot] = crl[t];
-      out[2 * M + slot] = cih[t];
-      out[3 * M + slot] = cil[t];
+      out[slot] = vrh;
+      out[M + slot] = vrl;
+      out[2 * M + slot] = vih;
+      out[3 * M + slot] = vil;
     }
   }
 }
