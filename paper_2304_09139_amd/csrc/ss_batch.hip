@@ -360,7 +360,7 @@ int setup_all(ss_ctx* ctx, int count, const ss_problem* probs, const ss_min_opts
     return SS_EINVAL;
   }
   // a configuration's units depend on its evaluation precision (the tiled and
-  // the walked n(k) pass differ): room for the most any of them can take
+  // the piece n(k) pass differ): room for the most any of them can take
   int64_t cap = 0;
   for (const HostSlot& h : hs) cap += max_units(h);
   *ucap = std::max<int64_t>(cap, (int64_t)U.size());

@@ -92,7 +92,7 @@ struct EvalSlot {
   double* smax;
   const int32_t* running;  // the minimiser's running word
   // the tiled d = 2 n(k) pass (nk2 != 0), in both precisions, instead of the
-  // piece walk above
+  // piece pass above
   int32_t nk2, R, t2_nrows;
   int64_t t2_chunk;
   const int32_t* t2_tiles;
