@@ -599,7 +599,7 @@ int make_cfg(ss_ctx* ctx, const ss_problem* p, Plan* pl, LaunchCfg* c, const Til
   const size_t per_particle = (size_t)p->d * c->R1 * 4 * sizeof(double);
   const size_t lds_budget = 64 * 1024;
   // d = 2 from R = kNk2MinR on: every n(k) pass (single, batched, FP64) is the
-  // tiled one, which stages 32 table rows whatever R is; the piece pass, which
+  // tiled one, which stages 32 table rows whatever R is; the piece walk, which
   // stages whole particle tables in LDS, is not used
   const bool tiles_only = p->d == 2 && pl->R >= kNk2MinR && pl->t2_ntiles > 0;
   if (16 * per_particle <= lds_budget) c->pt = 16;

@@ -31,19 +31,18 @@ struct NkUnit {
 constexpr int kSegLen = 8;        // wavevectors per lane in the n(k) pass
 static_assert(kSegLen % 2 == 0, "an n(k) piece stores exponents in +/- pairs");
 
-// Slot order of the n(k) partials: pieces are sorted by their stored length
-// (longest first), so the pieces longer than t are a prefix 0 .. cnt_t - 1 of
-// the piece list; stored wavevector t of piece s (t < len_s) is slot
-// off[t] + s, off[t] = sum_{t' < t} cnt_t'.  The M slots are a permutation of
-// the wavevectors in which the lanes of the n(k) pass write consecutive
-// addresses for every t.
+// Slot order of the n(k) partials: pieces are sorted by length (longest first),
+// so the pieces longer than t are a prefix 0 .. cnt_t - 1 of the piece list;
+// wavevector t of piece s (t < len_s) is slot off[t] + s, off[t] = sum_{t' < t}
+// cnt_t'.  The M slots are a permutation of the wavevectors in which the lanes
+// of the n(k) pass write consecutive addresses for every t.
 struct SlotOffsets {
   int32_t off[kSegLen];
 };
 
 // Everything that depends only on (d, R2): the half set in lexicographic (walk)
 // order and in canonical order, the map between them, the runs along the last
-// axis (gradient pass) and the n(k) pieces of at most kSegLen stored wavevectors.
+// axis (gradient pass) and the run pieces of length <= kSegLen (n(k) pass).
 struct Plan {
   int d = 0;
   int64_t R2 = 0, M = 0;
@@ -125,9 +124,9 @@ constexpr int kNkRounds = SS_NK_ROUNDS;     // most rounds of resident blocks in
 constexpr int64_t kNkMinChunk = 100;        // fewest particles per n(k) unit (on average) that a round may leave
 // d = 2 evaluations use the tiled n(k) pass (k_nk2) from R = kNk2MinR on; single
 // launches also from R = kNk2SmallR on when N <= kNk2SmallN, where the piece
-// pass's grid is small (measured: the piece pass is faster in between, e.g.
-// N = 8000 at R = 45, and in batches below R = 48, where the grid is full anyway
-// and the tiles' idle lanes outside H cost more)
+// walk's grid is small (measured: the walk is faster in between, e.g. N = 8000 at
+// R = 45, and in batches below R = 48, where the grid is full anyway and the
+// tiles' idle lanes outside H cost more)
 constexpr int kNk2MinR = 48;
 constexpr int kNk2SmallR = 16;
 constexpr int64_t kNk2SmallN = 2500;
