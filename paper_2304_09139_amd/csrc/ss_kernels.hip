@@ -142,31 +142,20 @@ __device__ __forceinline__ void nk_tile(const double* __restrict__ lds, int np, 
   }
 }
 
-template <int D, int PT>
-__device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t nseg, const NkUnit u,
+// a unit's particle tiles and stores for a wave whose widest piece spans L
+// exponents: the whole loop is instantiated per L, so that no accumulator is
+// merged across the widths (waves of a block may take different L: each runs
+// the same tiles and so the same barriers)
+template <int D, int PT, int L>
+__device__ __forceinline__ void nk_unit(const Span& sg, int64_t s, int len, bool plus, bool zero, const NkUnit u,
                                         const double* __restrict__ tab, int64_t N, int R1,
                                         double* __restrict__ part, int64_t M, const SlotOffsets& so,
                                         double* __restrict__ lds) {
   const int tid = threadIdx.x;
-  const int64_t s = (int64_t)u.block * kNkPieces + tid;
-  const Span sg = segs[s < nseg ? s : nseg - 1];
-  const int len = s < nseg ? sg.len : 0;
   const int epp = D * R1 * 4;  // doubles per particle
-  bool plus = true;  // the prefix-zero column
-#pragma unroll
-  for (int a = 0; a < D - 1; ++a) plus = plus && sg.n[a] == 0;
-  const bool zero = !plus && sg.n[D - 1] == 0;
-  const int nt = plus ? len : (len + 1) / 2;  // exponents of this lane's piece
-
   double crh[kSegLen], crl[kSegLen], cih[kSegLen], cil[kSegLen];
 #pragma unroll
   for (int t = 0; t < kSegLen; ++t) crh[t] = crl[t] = cih[t] = cil[t] = 0.0;
-
-  // the widest piece of the wave, in a scalar register, selects the unrolled loop
-  int wmax = nt;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o));
-  const int wl = __builtin_amdgcn_readfirstlane(wmax);
   const int64_t j0 = u.j0;
   const int64_t j1 = u.j1;
   for (int64_t tile = j0; tile < j1; tile += PT) {
@@ -178,17 +167,9 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
       lds[p * epp + ec] = p < np ? tab[(int64_t)ec * N + tile + p] : 0.0;
     }
     __syncthreads();
-    switch (wl) {
-      case 4:
-        if constexpr (kSegLen >= 8) nk_tile<D, 4>(lds, np, epp, R1, sg, crh, crl, cih, cil);
-        break;
-      case 3: nk_tile<D, 3>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
-      case 2: nk_tile<D, 2>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
-      case 1: nk_tile<D, 1>(lds, np, epp, R1, sg, crh, crl, cih, cil); break;
-      default: break;
-    }
+    if constexpr (L > 0) nk_tile<D, L>(lds, np, epp, R1, sg, crh, crl, cih, cil);
 #pragma unroll
-    for (int t = 0; t < kSegLen; ++t) {
+    for (int t = 0; t < 2 * L; ++t) {
       renorm(crh[t], crl[t]);
       renorm(cih[t], cil[t]);
     }
@@ -196,9 +177,9 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
   // slot order: for each stored index the lanes of a wave write consecutive slots
   double* out = part + (int64_t)u.row * 4 * M;
 #pragma unroll
-  for (int t = 0; t < kSegLen; ++t) {
+  for (int t = 0; t < 2 * L; ++t) {
     if (t < len) {
-      constexpr int kLast = kSegLen - 1;
+      constexpr int kLast = 2 * L - 1 > 0 ? 2 * L - 1 : 0;
       const int q1 = t + 1 < kLast ? t + 1 : kLast, q2 = 2 * t < kLast ? 2 * t : kLast;
       double vrh = crh[t], vrl = crl[t], vih = cih[t], vil = cil[t];
       if (zero && t >= 1) vrh = crh[q1], vrl = crl[q1], vih = cih[q1], vil = cil[q1];
@@ -209,6 +190,35 @@ __device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t n
       out[2 * M + slot] = vih;
       out[3 * M + slot] = vil;
     }
+  }
+}
+
+template <int D, int PT>
+__device__ __forceinline__ void nk_body(const Span* __restrict__ segs, int64_t nseg, const NkUnit u,
+                                        const double* __restrict__ tab, int64_t N, int R1,
+                                        double* __restrict__ part, int64_t M, const SlotOffsets& so,
+                                        double* __restrict__ lds) {
+  const int tid = threadIdx.x;
+  const int64_t s = (int64_t)u.block * kNkPieces + tid;
+  const Span sg = segs[s < nseg ? s : nseg - 1];
+  const int len = s < nseg ? sg.len : 0;
+  bool plus = true;  // the prefix-zero column
+#pragma unroll
+  for (int a = 0; a < D - 1; ++a) plus = plus && sg.n[a] == 0;
+  const bool zero = !plus && sg.n[D - 1] == 0;
+  const int nt = plus ? len : (len + 1) / 2;  // exponents of this lane's piece
+  // the widest piece of the wave, in a scalar register, selects the unit's loop
+  int wmax = nt;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o));
+  const int wl = __builtin_amdgcn_readfirstlane(wmax);
+  static_assert(kSegLen == 8, "the unit loops below cover widths 0 .. 4");
+  switch (wl) {
+    case 4: nk_unit<D, PT, 4>(sg, s, len, plus, zero, u, tab, N, R1, part, M, so, lds); break;
+    case 3: nk_unit<D, PT, 3>(sg, s, len, plus, zero, u, tab, N, R1, part, M, so, lds); break;
+    case 2: nk_unit<D, PT, 2>(sg, s, len, plus, zero, u, tab, N, R1, part, M, so, lds); break;
+    case 1: nk_unit<D, PT, 1>(sg, s, len, plus, zero, u, tab, N, R1, part, M, so, lds); break;
+    default: nk_unit<D, PT, 0>(sg, s, len, plus, zero, u, tab, N, R1, part, M, so, lds); break;
   }
 }
 
